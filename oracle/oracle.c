@@ -1,0 +1,308 @@
+/*
+ * Plain FP64 CPU oracle for the Heisenberg Lanczos hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or table with the HIP library; every routine here is written from
+ * the paper's text (Schnack, Hage, Schmidt, "Optimized implementation of the
+ * Lanczos method for magnetic systems"), in the paper's notation, with no
+ * blocking, fusion or reordering beyond what the paper states.
+ *
+ * Conventions (readings of the paper, listed in the design notes):
+ *   - site index u = 1..N in the paper is u-1 = 0..N-1 here;
+ *   - digits a_u = s - m_u in {0..2s}; the spin is passed as two_s = 2s;
+ *   - A = sum_u a_u, i.e. M = N s - A (Sec. 3);
+ *   - basis indices are 0-based: index = (paper's 1-based index) - 1;
+ *   - the Hamiltonian sum of Eq. (E-2-1) runs over unordered pairs u<v.
+ *
+ * Every function reports failure by a negative return value; none aborts.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EXPORT __attribute__((visibility("default")))
+
+/* ---------------------------------------------------------------------------
+ * Count table D(n, A), Sec. 3, Eq. (E-3-c).
+ *
+ * D(n, A) is the number of n-site digit strings over {0..2s} whose digits sum
+ * to A.  The paper builds it by the recursion
+ *     D(n, A) = sum_{k=0}^{2s} D(n-1, A-k),
+ * seeded with D(1, A) = 1 for A = 0..2s, and D(n, A) = 0 whenever A lies
+ * outside {0, .., 2 n s}.  The table is stored as D[n * (N*two_s + 1) + A]
+ * for n = 0..N, A = 0..N*two_s.  Row n = 0 holds D(0, 0) = 1 (the empty
+ * string), which the recursion for n = 1 reproduces the paper's seed from.
+ * Returns 0, or -1 if an entry would overflow int64.
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int or_count_table(int N, int two_s, int64_t *D)
+{
+    const int W = N * two_s + 1;
+    memset(D, 0, sizeof(int64_t) * (size_t)(N + 1) * (size_t)W);
+    D[0] = 1;
+    for (int n = 1; n <= N; ++n) {
+        for (int A = 0; A <= n * two_s; ++A) {
+            int64_t sum = 0;
+            for (int k = 0; k <= two_s; ++k) {
+                int prev = A - k;
+                if (prev < 0 || prev > (n - 1) * two_s)
+                    continue; /* zero outside the valid range */
+                int64_t term = D[(size_t)(n - 1) * W + prev];
+                if (term > INT64_MAX - sum)
+                    return -1;
+                sum += term;
+            }
+            D[(size_t)n * W + A] = sum;
+        }
+    }
+    return 0;
+}
+
+/* D(n, A) with the paper's zero padding outside the valid index range. */
+static int64_t count_at(const int64_t *D, int N, int two_s, int n, int A)
+{
+    if (n < 0 || n > N || A < 0 || A > n * two_s)
+        return 0;
+    return D[(size_t)n * (N * two_s + 1) + A];
+}
+
+/* ---------------------------------------------------------------------------
+ * Decoding i -> |a_1 .. a_N>, Sec. 3.1.
+ *
+ * Sites are fixed from the highest (k = N) down to k = 2.  At site k the
+ * states that remain are split by the digit n placed there; the block with
+ * digit n holds D(k-1, A_k - n) states, where A_k is the digit sum still to be
+ * placed on sites 1..k.  The digit is the first n whose block contains the
+ * remaining offset.  Site 1 takes whatever sum is left.  `a` receives
+ * a[u-1] = a_u.  Returns 0, or -1 if i is not in [0, D(N, A)).
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int or_unrank(int N, int two_s, int A, const int64_t *D, int64_t i,
+                        int *a)
+{
+    if (i < 0 || i >= count_at(D, N, two_s, N, A))
+        return -1;
+    int64_t offset = i; /* states still to skip inside the current block */
+    int Ak = A;
+    for (int k = N; k >= 2; --k) {
+        int placed = -1;
+        for (int n = 0; n <= two_s; ++n) {
+            int64_t block = count_at(D, N, two_s, k - 1, Ak - n);
+            if (offset < block) {
+                placed = n;
+                break;
+            }
+            offset -= block;
+        }
+        if (placed < 0)
+            return -1;
+        a[k - 1] = placed;
+        Ak -= placed;
+    }
+    a[0] = Ak;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Encoding |a_1 .. a_N> -> i, Sec. 3.2.
+ *
+ * The index is the number of basis states that sort before the given one.
+ * Going from the highest site k = N down to k = 2, every state that agrees on
+ * sites k+1..N but carries a smaller digit n < a_k on site k sorts before it;
+ * there are D(k-1, A_k - n) of them for each such n.  Returns the 0-based
+ * index, or -1 if a digit is out of {0..2s} or the digits do not sum to A.
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int64_t or_rank(int N, int two_s, int A, const int64_t *D,
+                          const int *a)
+{
+    int sum = 0;
+    for (int u = 0; u < N; ++u) {
+        if (a[u] < 0 || a[u] > two_s)
+            return -1;
+        sum += a[u];
+    }
+    if (sum != A)
+        return -1;
+    int64_t index = 0;
+    int Ak = A;
+    for (int k = N; k >= 2; --k) {
+        for (int n = 0; n < a[k - 1]; ++n)
+            index += count_at(D, N, two_s, k - 1, Ak - n);
+        Ak -= a[k - 1];
+    }
+    return index;
+}
+
+/* ---------------------------------------------------------------------------
+ * Successor of a basis state, Sec. 3.1 ("balls in boxes").
+ *
+ * (1) find the leftmost box k holding a ball whose right neighbour k+1 holds
+ *     fewer than 2s balls; if there is none the state is the last one;
+ * (2) move one ball from box k to box k+1;
+ * (3) collect the balls of boxes 1..k and refill them from the left, at most
+ *     2s per box.
+ * Returns 1 and updates `a` in place, or 0 if `a` has no successor.
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int or_successor(int N, int two_s, int *a)
+{
+    int k = -1;
+    for (int u = 0; u + 1 < N; ++u) {
+        if (a[u] > 0 && a[u + 1] < two_s) {
+            k = u;
+            break;
+        }
+    }
+    if (k < 0)
+        return 0;
+    a[k] -= 1;
+    a[k + 1] += 1;
+    int balls = 0;
+    for (int u = 0; u <= k; ++u) {
+        balls += a[u];
+        a[u] = 0;
+    }
+    for (int u = 0; u <= k && balls > 0; ++u) {
+        int put = balls < two_s ? balls : two_s;
+        a[u] = put;
+        balls -= put;
+    }
+    return 1;
+}
+
+/* ---------------------------------------------------------------------------
+ * Row of H applied to a vector: the gather form of Eq. (E-4-b), Sec. 4.
+ *
+ * H = - sum_{u<v} J_uv s(u).s(v), Eq. (E-2-1), with
+ *     s(u).s(v) = s_z(u) s_z(v) + (s+(u) s-(v) + s-(u) s+(v)) / 2.
+ * Acting on the final basis state |i> gives
+ *   - the diagonal element  -sum_{u<v} J_uv m_u m_v  with m = s - a;
+ *   - for each bond and each of the two ladder terms that does not annihilate
+ *     |i>, one state |j> and the element <i|H|j>.  With digits a = s - m the
+ *     standard ladder algebra gives
+ *         s+(u) s-(v): a_u -> a_u - 1, a_v -> a_v + 1,
+ *                      factor sqrt(a_u (2s - a_u + 1)) sqrt((2s - a_v)(a_v + 1));
+ *         s-(u) s+(v): the same with u and v exchanged;
+ *     each multiplied by -J_uv / 2.
+ * The output entry is y_i = sum over those j of <i|H|j> x_j; j comes from the
+ * encoding above.  Only y_i is written, so rows are independent (the paper's
+ * point about avoiding write conflicts).
+ *
+ * `J` is the dense N x N coupling matrix (row-major); only u<v entries are
+ * read.  `cur` is the digit string of row i and is left unchanged; `work`
+ * must hold N ints.
+ * ------------------------------------------------------------------------- */
+static double apply_row(int N, int two_s, int A, const int64_t *D,
+                        const double *J, const double *x, int64_t i,
+                        const int *cur, int *work)
+{
+    const double s = 0.5 * two_s;
+    double diag = 0.0;
+    double y = 0.0;
+    for (int u = 0; u < N; ++u) {
+        for (int v = u + 1; v < N; ++v) {
+            double Juv = J[(size_t)u * N + v];
+            if (Juv == 0.0)
+                continue;
+            double mu = s - cur[u], mv = s - cur[v];
+            diag += -Juv * mu * mv;
+            /* s+(u) s-(v) */
+            if (cur[u] >= 1 && cur[v] <= two_s - 1) {
+                double f = sqrt((double)cur[u] * (two_s - cur[u] + 1)) *
+                           sqrt((double)(two_s - cur[v]) * (cur[v] + 1));
+                memcpy(work, cur, sizeof(int) * (size_t)N);
+                work[u] -= 1;
+                work[v] += 1;
+                int64_t j = or_rank(N, two_s, A, D, work);
+                y += -0.5 * Juv * f * x[j];
+            }
+            /* s-(u) s+(v) */
+            if (cur[v] >= 1 && cur[u] <= two_s - 1) {
+                double f = sqrt((double)cur[v] * (two_s - cur[v] + 1)) *
+                           sqrt((double)(two_s - cur[u]) * (cur[u] + 1));
+                memcpy(work, cur, sizeof(int) * (size_t)N);
+                work[v] -= 1;
+                work[u] += 1;
+                int64_t j = or_rank(N, two_s, A, D, work);
+                y += -0.5 * Juv * f * x[j];
+            }
+        }
+    }
+    return diag * x[i] + y;
+}
+
+/* ---------------------------------------------------------------------------
+ * y = H x on the whole subspace H(M), Eqs. (E-4-a)/(E-4-b), Sec. 4.
+ *
+ * The loop over final rows i is the outer loop, as the paper prescribes.
+ * Rows are visited in order: the first row of a chunk is decoded with
+ * or_unrank, the following ones are reached with or_successor.  With OpenMP
+ * the chunks of rows run on separate threads (the paper's shared-memory
+ * scheme); without it the loop is serial.  Returns 0, or -1 on bad input.
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int or_apply(int N, int two_s, int A, const int64_t *D,
+                       const double *J, const double *x, double *y)
+{
+    const int64_t dim = count_at(D, N, two_s, N, A);
+    if (dim <= 0)
+        return -1;
+    const int64_t chunk = 4096;
+    const int64_t nchunks = (dim + chunk - 1) / chunk;
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < nchunks; ++c) {
+        int *cur = (int *)malloc(sizeof(int) * (size_t)N);
+        int *work = (int *)malloc(sizeof(int) * (size_t)N);
+        int64_t first = c * chunk;
+        int64_t last = first + chunk < dim ? first + chunk : dim;
+        if (!cur || !work || or_unrank(N, two_s, A, D, first, cur) != 0) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            for (int64_t i = first; i < last; ++i) {
+                y[i] = apply_row(N, two_s, A, D, J, x, i, cur, work);
+                if (i + 1 < last)
+                    or_successor(N, two_s, cur);
+            }
+        }
+        free(cur);
+        free(work);
+    }
+    return failed ? -1 : 0;
+}
+
+/* The same rows as or_apply, but only for the listed row indices: used to
+ * check single rows of very large problems.  Each row is decoded on its own. */
+OR_EXPORT int or_apply_rows(int N, int two_s, int A, const int64_t *D,
+                            const double *J, const double *x,
+                            const int64_t *rows, int64_t nrows, double *y)
+{
+    int failed = 0;
+#pragma omp parallel
+    {
+        int *cur = (int *)malloc(sizeof(int) * (size_t)N);
+        int *work = (int *)malloc(sizeof(int) * (size_t)N);
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < nrows; ++r) {
+            if (!cur || !work || or_unrank(N, two_s, A, D, rows[r], cur) != 0) {
+#pragma omp atomic write
+                failed = 1;
+                continue;
+            }
+            y[r] = apply_row(N, two_s, A, D, J, x, rows[r], cur, work);
+        }
+        free(cur);
+        free(work);
+    }
+    return failed ? -1 : 0;
+}
+
+/* Number of threads the OpenMP runtime would use (1 without OpenMP). */
+OR_EXPORT int or_max_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
