@@ -1,0 +1,248 @@
+/*
+ * hm.h -- C ABI of the MI355X (gfx950) Lanczos hot path for isotropic
+ * Heisenberg spin systems in a subspace of fixed total magnetic quantum number.
+ *
+ * Model (Sec. 2, Eq. (E-2-1)):  H = - sum_{u<v} J_uv s(u).s(v), all spins s.
+ * The basis of the subspace H(M) is the set of product states |a_1..a_N> with
+ * digits a_u = s - m_u in {0..2s} and digit sum A = N s - M (Sec. 3), numbered
+ * in ascending order of the base-(2s+1) number sum_u a_u (2s+1)^(u-1), site 1
+ * least significant (Eq. (E-3-a)).  Indices are 0-based (the paper counts from
+ * 1).  Sites are numbered 0..N-1 here (site u here is the paper's u+1).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an int status: HM_OK (0) or a negative HM_E* code.
+ *     On failure hm_last_error() returns a message for the calling thread.
+ *     No C++ exception crosses this boundary.
+ *   - Spin and magnetization are passed doubled: two_s = 2s >= 1 and
+ *     two_M = 2M, so half-integers are exact.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the current device.  The caller owns every buffer.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Device work is
+ *     enqueued on it.  Calls that return host results synchronize the stream
+ *     before returning; hm_apply, hm_unrank_dev and hm_rank_dev return right
+ *     after enqueueing.
+ *   - Coupling matrices J are host arrays of N*N doubles, row-major, which
+ *     must be symmetric with a zero diagonal and finite entries (HM_EINVAL
+ *     otherwise).  Only pairs with J_uv != 0 become bonds.
+ *   - A basis handle is immutable once created (it keeps an internal,
+ *     mutex-protected cache of uploaded coupling lists) and may be shared by
+ *     threads.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define HM_OK 0
+#define HM_EINVAL (-1)     /* invalid argument                                 */
+#define HM_ERANGE (-2)     /* size not supported (bits, dimension, tables)     */
+#define HM_ENOMEM (-3)     /* host or device allocation failed                 */
+#define HM_EDEVICE (-4)    /* HIP runtime error or no usable gfx950 device     */
+#define HM_EWORKSPACE (-5) /* workspace smaller than hm_lanczos_workspace says */
+
+/* Element type of device vectors. */
+#define HM_F64 0
+#define HM_F32 1
+
+/* Lanczos precision policy (north of the vector storage type):
+ *   HM_PREC_F64       vectors, matrix elements and dots in FP64;
+ *   HM_PREC_F32_MIXED vectors stored and H x matrix elements applied in FP32;
+ *                     alpha/beta dots, norms, reorthogonalization
+ *                     coefficients and ground-state accumulation in FP64. */
+#define HM_PREC_F64 0
+#define HM_PREC_F32_MIXED 1
+
+typedef struct hm_basis_s *hm_basis;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *hm_last_error(void);
+
+/* Library version string. */
+const char *hm_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Count table, Sec. 3 Eq. (E-3-c): D(n, A) is the number of n-digit strings
+ * over {0..2s} with digit sum A; zero for A outside 0..2ns.
+ * Writes D(n, A) to *out.  HM_EINVAL: n < 0, two_s < 1, null out.
+ * HM_ERANGE: the value does not fit int64.
+ * ------------------------------------------------------------------------- */
+int hm_count(int32_t n, int32_t two_s, int32_t A, int64_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Basis of H(M) (Sec. 3).  Builds the count table and the prefix tables the
+ * encoding and decoding use (host memory; device copies are made on first
+ * device use).  A = (N*two_s - two_M) / 2.
+ * HM_EINVAL: N < 1, two_s < 1, N*two_s - two_M odd, or A outside 0..N*two_s;
+ * null out.  HM_ERANGE: N * bits(2s) > 64 (a state does not fit the packed
+ * 64-bit format below) or dim >= 2^62.
+ * ------------------------------------------------------------------------- */
+int hm_basis_init(int32_t N, int32_t two_s, int32_t two_M, hm_basis *out);
+
+/* Releases the handle, its tables and cached device data.  Work enqueued
+ * with the handle must have completed.  NULL is accepted. */
+int hm_basis_free(hm_basis h);
+
+/* Dimension D(N, A) of the subspace. */
+int hm_basis_dim(hm_basis h, int64_t *dim);
+
+/* N, two_s, A, and the bits per digit of the packed state format. */
+int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
+                  int32_t *bits_per_digit);
+
+/* ---------------------------------------------------------------------------
+ * Decoding i -> |a_1..a_N> (Sec. 3.1) and encoding |a> -> i (Sec. 3.2) on the
+ * host.  digits is a host array of N bytes, digits[u] = a_{u+1}.
+ * hm_unrank: HM_EINVAL if i is outside [0, dim) or digits is null.
+ * hm_rank:   HM_EINVAL if a digit exceeds 2s or the digits do not sum to A.
+ * ------------------------------------------------------------------------- */
+int hm_unrank(hm_basis h, int64_t i, uint8_t *digits);
+int hm_rank(hm_basis h, const uint8_t *digits, int64_t *i);
+
+/* ---------------------------------------------------------------------------
+ * The same on the device, for n states at once.  Packed state format: a
+ * uint64 holding digit a_{u+1} in bits [u*b, (u+1)*b), b = bits_per_digit
+ * (b = 1 for s = 1/2, 2 for s = 1 and 3/2, 3 for s = 2..7/2, ...); unused high
+ * bits are zero.
+ * hm_unrank_dev: d_idx (device, n int64) -> d_state (device, n uint64);
+ *   an index outside [0, dim) yields the state ~0 (all bits set).
+ * hm_rank_dev: d_state -> d_idx; a state that is not in the subspace (digit
+ *   above 2s, wrong digit sum, stray high bits) yields -1.
+ * n = 0 is a no-op.  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------- */
+int hm_unrank_dev(hm_basis h, const int64_t *d_idx, int64_t n,
+                  uint64_t *d_state, void *stream);
+int hm_rank_dev(hm_basis h, const uint64_t *d_state, int64_t n,
+                int64_t *d_idx, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * y = H x on the whole subspace, the gather form of Sec. 4 Eq. (E-4-b): each
+ * output row i is produced by applying H to the basis state |i>, so every
+ * entry of y is written by exactly one GPU lane and no atomics are used.
+ * d_x, d_y: device arrays of dim elements of type `dtype` (HM_F64 or HM_F32);
+ * they must not overlap.  With HM_F32 the matrix elements are rounded to
+ * FP32 once and applied in FP32.  Asynchronous on `stream`.
+ * HM_EINVAL: bad J (see above), null pointers, unknown dtype, d_x == d_y.
+ * ------------------------------------------------------------------------- */
+int hm_apply(hm_basis h, const double *J, const void *d_x, void *d_y,
+             int32_t dtype, void *stream);
+
+/* hm_apply with an explicit choice of H x kernel: 1 = the generic digit
+ * kernel (any s), 2 = the spin-1/2 block kernel (s = 1/2 only; HM_EINVAL
+ * otherwise).  Both give y = H x; this entry point exists to cross-check them
+ * and to time them separately. */
+int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y,
+                    int32_t dtype, int32_t kernel, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Lanczos iteration (Sec. 1 and Sec. 4 name the method; the paper does not
+ * write it out).  Paige's ordering:
+ *   v_1 = v0/|v0|;  w = H v_k - beta_{k-1} v_{k-1};  alpha_k = <w, v_k>;
+ *   w -= alpha_k v_k;  [full_reorth: twice w -= V_k (V_k^T w)];
+ *   beta_k = |w|;  stop if beta_k <= breakdown_tol * max_{j<=k}(|alpha_j|, beta_j);
+ *   v_{k+1} = w / beta_k.
+ * E0 is the lowest eigenvalue of the tridiagonal T with diagonal alpha_1..k
+ * and off-diagonal beta_1..k-1, found on the host in FP64 (Sturm bisection).
+ * ------------------------------------------------------------------------- */
+typedef struct hm_lanczos_opts {
+    int32_t precision;    /* HM_PREC_F64 or HM_PREC_F32_MIXED               */
+    int32_t full_reorth;  /* 1: classical Gram-Schmidt twice vs all v_j     */
+    double breakdown_tol; /* relative; <= 0 selects 1e-12                   */
+    int32_t use_graph;    /* 1: capture all steps in one hipGraph           */
+    int32_t kernel;       /* 0: automatic choice of H x kernel; 1: generic
+                             digit kernel; 2: spin-1/2 block kernel (if the
+                             basis is spin 1/2)                              */
+} hm_lanczos_opts;
+
+/* Bytes of device workspace hm_lanczos / hm_lanczos_ritz need. */
+int hm_lanczos_workspace(hm_basis h, int32_t steps, const hm_lanczos_opts *o,
+                         size_t *bytes);
+
+/* Runs up to `steps` steps from the device FP64 start vector d_v0 (dim
+ * entries, any nonzero norm; it is normalized internally and not modified).
+ * Outputs (host): alpha[steps], beta[steps] (entries past *steps_done are
+ * zero), *E0, *steps_done.  A breakdown is not an error: HM_OK with
+ * *steps_done < steps.  d_work: device workspace of work_bytes bytes (>=
+ * hm_lanczos_workspace).  Synchronizes `stream`.
+ * HM_EINVAL: bad J, steps < 1, null pointers, zero start vector.
+ * HM_EWORKSPACE: work_bytes too small. */
+int hm_lanczos(hm_basis h, const double *J, const double *d_v0, int32_t steps,
+               const hm_lanczos_opts *o, void *d_work, size_t work_bytes,
+               double *alpha, double *beta, double *E0, int32_t *steps_done,
+               void *stream);
+
+/* Ground-state recompute: repeats exactly the recurrence hm_lanczos ran
+ * (same J, d_v0, options and workspace size, steps_done steps) and
+ * accumulates psi = sum_k c_k v_k in FP64 on the device, then normalizes it.
+ * c: host array of steps_done doubles (an eigenvector of T).  d_psi: device
+ * FP64 array of dim entries (output).  alpha_out/beta_out (host, may be
+ * NULL) receive the recomputed coefficients, which equal the first pass's
+ * bit for bit.  Synchronizes `stream`. */
+int hm_lanczos_ritz(hm_basis h, const double *J, const double *d_v0,
+                    int32_t steps_done, const double *c,
+                    const hm_lanczos_opts *o, void *d_work, size_t work_bytes,
+                    double *d_psi, double *alpha_out, double *beta_out,
+                    void *stream);
+
+/* Lowest eigenpair of the k x k tridiagonal matrix diag(alpha) +
+ * offdiag(beta[0..k-2]) on the host in FP64 (bisection on the Sturm sequence,
+ * then inverse iteration).  evec (may be NULL): k doubles, unit norm, first
+ * nonzero component made positive. */
+int hm_tridiag_lowest(int32_t k, const double *alpha, const double *beta,
+                      double *eval, double *evec);
+
+/* ---------------------------------------------------------------------------
+ * Bond correlations <psi| s(u).s(v) |psi> for nb bonds (uv: host int32
+ * [nb][2], 0 <= u != v < N), psi a device FP64 vector of dim entries.
+ * By Hellmann-Feynman dE0/dJ_uv = -<s(u).s(v)> for the normalized ground
+ * state.  corr: host array of nb doubles.  Rows are processed in the gather
+ * form of Eq. (E-4-b); per-bond sums are reduced in a fixed order (bitwise
+ * reproducible).  Synchronizes `stream`.
+ * ------------------------------------------------------------------------- */
+int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
+                 double *corr, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched Lanczos: ninst independent problems, each with nvec start vectors,
+ * solved together in FP32-mixed precision by one persistent (cooperative)
+ * kernel launch that runs all steps; the multi-vector product H X shares one
+ * decoding and one encoding per row among the nvec vectors.
+ *   bases[k]     basis handle of instance k (any mix of N, s, M);
+ *   J[k]         host N_k x N_k coupling matrix;
+ *   d_v0[k]      device FP64 array [dim_k][nvec] (row-major: the nvec start
+ *                vectors interleaved, entry (i, r) at i*nvec + r);
+ *   nvec         1..16 vectors per instance;
+ *   alpha, beta  host arrays [ninst][nvec][steps];
+ *   E0           host array [ninst][nvec];
+ *   steps_done   host array [ninst][nvec].
+ * Each (instance, vector) pair runs its own recurrence; a breakdown stops
+ * only that pair.  d_work: device workspace of at least
+ * hm_lanczos_batched_workspace bytes.  Synchronizes `stream`.
+ * ------------------------------------------------------------------------- */
+int hm_lanczos_batched_workspace(int32_t ninst, const hm_basis *bases,
+                                 int32_t nvec, int32_t steps, size_t *bytes);
+int hm_lanczos_batched(int32_t ninst, const hm_basis *bases,
+                       const double *const *J, const double *const *d_v0,
+                       int32_t nvec, int32_t steps, double breakdown_tol,
+                       void *d_work, size_t work_bytes, double *alpha,
+                       double *beta, double *E0, int32_t *steps_done,
+                       void *stream);
+
+/* Per-kernel timing of the last hm_lanczos call on this thread, measured
+ * with HIP events on the call's stream: total milliseconds and launch count
+ * of the H x pass (the dominant kernel) and of the whole step loop.  Timing
+ * is recorded only when enabled with hm_set_timing(1) (events add a little
+ * overhead and prevent graph capture of the steps). */
+int hm_set_timing(int32_t enable);
+int hm_last_timing(double *hx_ms, int32_t *hx_launches, double *loop_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HM_H */

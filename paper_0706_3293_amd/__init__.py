@@ -1,0 +1,11 @@
+"""MI355X-native Lanczos hot path for Heisenberg spin systems in H(M).
+
+The product path is libhm.so (HIP kernels for gfx950 behind the C ABI in
+include/hm.h); this package is its thin Python binding:
+
+  Basis            subspace H(M), host/device encoding and decoding, H x,
+                   Lanczos, ground-state recompute, bond correlations
+  GroundStateEnergy  torch.autograd.Function for E0(J) with dE0/dJ = -<s.s>
+  lanczos_batched  many instances and start vectors in one persistent launch
+"""
+from .api import Basis, LanczosResult, count, last_timing, set_timing, tridiag_lowest  # noqa: F401

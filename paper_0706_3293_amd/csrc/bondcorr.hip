@@ -1,0 +1,135 @@
+// Bond correlations <psi| s(u).s(v) |psi> for a list of bonds: the backward
+// kernel of the ground-state energy (dE0/dJ_uv = -<s(u).s(v)>).
+//
+// Rows are visited in the gather form of Eq. (E-4-b): the lane that owns row
+// i decodes |i>, and for every bond adds psi_i times the row i of s(u).s(v)
+// applied to psi (diagonal m_u m_v psi_i plus the two ladder terms, each
+// 1/2 * ladder factors * psi_j).  Per-bond sums are reduced wave by wave in a
+// fixed butterfly order into per-wave LDS slots, then per workgroup, then
+// over workgroups by a single workgroup: no atomics, bitwise reproducible.
+#include "device_common.h"
+#include "hm_internal.h"
+
+namespace hm {
+
+constexpr int kCorrMaxBonds = 1024;
+constexpr int kCorrBlock = 256;
+
+template <typename I, int B>
+__global__ __launch_bounds__(kCorrBlock) void bond_corr_kernel(
+    const I *__restrict__ gprefix, const double *__restrict__ gladder,
+    const int32_t *__restrict__ uv, int nb, int N, int A, int two_s, I dim,
+    const double *__restrict__ psi, double *__restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int plen = N * (A + 1) * (two_s + 1);
+    const int nwaves = blockDim.x >> 6;
+    I *P = reinterpret_cast<I *>(smem);
+    size_t off = ((plen * sizeof(I) + 15) / 16) * 16;
+    double *F = reinterpret_cast<double *>(smem + off);
+    off += ((two_s + 2) * sizeof(double) + 15) / 16 * 16;
+    double *acc = reinterpret_cast<double *>(smem + off);   // [nwaves][nb]
+    for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = gprefix[t];
+    for (int t = threadIdx.x; t < two_s + 2; t += blockDim.x) F[t] = gladder[t];
+    for (int t = threadIdx.x; t < nwaves * nb; t += blockDim.x) acc[t] = 0.0;
+    __syncthreads();
+    const Prefix<I> pv{P, A + 1, two_s + 1};
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    I first, last;
+    block_rows<I>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, dim, first, last);
+    // every lane runs the same number of iterations so the wave reductions
+    // below see all 64 lanes; lanes past `last` contribute zero
+    const I span = last - first;
+    const I iters = (span + blockDim.x - 1) / blockDim.x;
+    for (I it = 0; it < iters; ++it) {
+        const I row = first + it * blockDim.x + threadIdx.x;
+        const bool live = row < last;
+        const uint64_t st = live ? unrank_state<I, B>(row, pv, N, A, two_s) : 0;
+        const double pi = live ? psi[row] : 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const int u = uv[2 * b], v = uv[2 * b + 1];
+            double c = 0.0;
+            if (live) {
+                const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
+                double s = 0.25 * (double)((two_s - 2 * au) * (two_s - 2 * av)) * pi;
+                if (au >= 1 && av < two_s)
+                    s += 0.5 * F[au] * F[av + 1] * psi[row + move_delta<I, B>(st, u, v, -1, pv)];
+                if (av >= 1 && au < two_s)
+                    s += 0.5 * F[av] * F[au + 1] * psi[row + move_delta<I, B>(st, u, v, +1, pv)];
+                c = pi * s;
+            }
+            c = wave_sum(c);
+            if (lane == 0) acc[wid * nb + b] += c;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += acc[w * nb + b];
+        partial[(size_t)blockIdx.x * nb + b] = s;
+    }
+}
+
+__global__ __launch_bounds__(kCorrBlock) void bond_corr_finish(const double *__restrict__ partial,
+                                                               int nblocks, int nb,
+                                                               double *__restrict__ out) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nblocks; ++k) s += partial[(size_t)k * nb + b];
+        out[b] = s;
+    }
+}
+
+int bond_corr_blocks(const Basis *b) {
+    int64_t g = (b->dim + kCorrBlock - 1) / kCorrBlock;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    if (g >= kXcds) g -= g % kXcds;
+    return (int)g;
+}
+
+int bond_corr_max_bonds() { return kCorrMaxBonds; }
+
+template <typename I, int B>
+static void launch_t(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
+                     double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+    const size_t plen = b->prefix_len();
+    size_t lds = ((plen * sizeof(I) + 15) / 16) * 16;
+    lds += ((b->two_s + 2) * sizeof(double) + 15) / 16 * 16;
+    lds += (size_t)(kCorrBlock / 64) * nb * sizeof(double);
+    hipLaunchKernelGGL((bond_corr_kernel<I, B>), dim3(nblocks), dim3(kCorrBlock), lds, st,
+                       (const I *)b->d_prefix, b->d_ladder, d_uv, nb, b->N, b->A, b->two_s,
+                       (I)b->dim, d_psi, d_partial);
+    hipLaunchKernelGGL(bond_corr_finish, dim3((nb + kCorrBlock - 1) / kCorrBlock),
+                       dim3(kCorrBlock), 0, st, d_partial, nblocks, nb, d_out);
+}
+
+template <typename I>
+static int launch_bits(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
+                       double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+    switch (b->bits) {
+        case 1: launch_t<I, 1>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 2: launch_t<I, 2>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 3: launch_t<I, 3>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 4: launch_t<I, 4>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 5: launch_t<I, 5>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 6: launch_t<I, 6>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 7: launch_t<I, 7>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 8: launch_t<I, 8>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        default: return fail(HM_ERANGE, "bits per digit %d unsupported", b->bits);
+    }
+    return HM_OK;
+}
+
+int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
+                     double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+    const size_t lds = ((b->prefix_len() * (b->idx32 ? 4 : 8) + 15) / 16) * 16 +
+                       ((b->two_s + 2) * sizeof(double) + 15) / 16 * 16 +
+                       (size_t)(kCorrBlock / 64) * nb * sizeof(double);
+    if (lds > 64 * 1024) return fail(HM_ERANGE, "bond correlation tables exceed LDS");
+    HM_TRY(b->idx32 ? launch_bits<uint32_t>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st)
+                    : launch_bits<uint64_t>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st));
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+}
+
+}  // namespace hm

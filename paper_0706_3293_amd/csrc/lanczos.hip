@@ -1,0 +1,683 @@
+// Lanczos three-term recurrence on the GPU (Paige's ordering), the
+// ground-state recompute pass and the host tridiagonal eigensolver.
+//
+// Step k (0-based) with v_k = sigma_k r_k kept as a raw vector r_k and a
+// device scalar sigma_k:
+//   pass A  w = sigma_k (H r_k) - cprev_k r_{k-1}      [fused in the H x kernel]
+//           alpha partials  <w, v_k>                   [same kernel, FP64]
+//   finish  alpha_k = sum of partials                  [one workgroup, fixed order]
+//   pass B  w -= alpha_k v_k,  partials of |w|^2       [FP64 arithmetic]
+//   [reorth twice: h = V^T w, w -= V h]
+//   finish  beta_k = |w|; breakdown test; sigma_{k+1} = 1/beta_k,
+//           cprev_{k+1} = beta_k sigma_k
+// The raw buffers rotate (r_{k+1} is w), so the 1/beta normalization never
+// costs a vector pass.  All reductions are per-workgroup partials summed in a
+// fixed order: two runs with the same inputs give the same bits, which the
+// recompute pass relies on.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
+#include "hm_internal.h"
+
+namespace hm {
+
+int launch_hx_generic(const Basis *b, const Couplings *c, int dtype, const HxPass &p,
+                      hipStream_t st);
+int hx_generic_grid(const Basis *b);
+int launch_hx_half(const Basis *b, const Couplings *c, int dtype, const HxPass &p,
+                   hipStream_t st);
+int hx_half_grid(const Basis *b);
+bool half_supported(const Basis *b);
+
+int choose_kernel(const Basis *b, int requested) {
+    if (requested == 1) return 1;
+    if (requested == 2) return half_supported(b) ? 2 : -1;
+    return half_supported(b) ? 2 : 1;
+}
+
+int hx_partial_count(const Basis *b, int kernel) {
+    return kernel == 2 ? hx_half_grid(b) : hx_generic_grid(b);
+}
+
+int launch_hx(const Basis *b, const Couplings *c, int dtype, int kernel, const HxPass &p,
+              hipStream_t st) {
+    if (kernel == 2) return launch_hx_half(b, c, dtype, p, st);
+    return launch_hx_generic(b, c, dtype, p, st);
+}
+
+// Device-side scalars of one Lanczos run.
+struct LzDev {
+    int stopped;     // steps done when a breakdown ended the run; 0 while running
+    int bad_start;   // 1 if |v0| == 0
+    double tol;
+    double scale;    // running max(|alpha_j|, beta_j)
+    double norm0;    // |v0|
+    double psi_norm;
+};
+
+struct Layout {
+    size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, r0, r1, r2, V, total;
+    int grid_vec, nparts;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int vec_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    g = std::min<int64_t>(g, kMaxGrid);
+    g = std::max<int64_t>(g, 1);
+    if (g >= kXcds) g -= g % kXcds;
+    return (int)g;
+}
+
+static Layout layout(const Basis *b, int steps, int prec, int reorth, int kernel) {
+    Layout L{};
+    const size_t es = prec == HM_PREC_F64 ? 8 : 4;
+    L.grid_vec = vec_grid(b->dim);
+    const int ghx = hx_partial_count(b, kernel);
+    L.nparts = std::max(L.grid_vec, ghx);
+    size_t partial_len = (size_t)L.nparts;
+    if (reorth) partial_len = std::max(partial_len, (size_t)L.grid_vec * (size_t)steps);
+    size_t off = 0;
+    L.lz = off; off = align256(off + sizeof(LzDev));
+    L.alpha = off; off = align256(off + sizeof(double) * steps);
+    L.beta = off; off = align256(off + sizeof(double) * steps);
+    L.sigma = off; off = align256(off + sizeof(double) * (steps + 1));
+    L.cprev = off; off = align256(off + sizeof(double) * (steps + 1));
+    L.coef = off; off = align256(off + sizeof(double) * steps);
+    L.hcoef = off; off = align256(off + sizeof(double) * (steps + 1));
+    L.partial = off; off = align256(off + sizeof(double) * partial_len);
+    L.r0 = off; off = align256(off + es * (size_t)b->dim);
+    L.r1 = off; off = align256(off + es * (size_t)b->dim);
+    L.r2 = off; off = align256(off + es * (size_t)b->dim);
+    L.V = off;
+    if (reorth) off = align256(off + es * (size_t)b->dim * (size_t)steps);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels.  Each workgroup owns one contiguous slice of rows (XCD-aware
+// order) and writes one FP64 partial.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void sumsq_kernel(const T *__restrict__ x, int64_t n,
+                                                       double *__restrict__ partial,
+                                                       const int *__restrict__ stopped) {
+    if (stopped && *stopped) return;
+    __shared__ double red[16];
+    int64_t first, last;
+    block_rows<int64_t>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, n, first, last);
+    double s = 0.0;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+        const double v = (double)x[i];
+        s += v * v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Sum of n partials in a fixed order by one workgroup.
+__device__ double fixed_sum(const double *__restrict__ partial, int n, double *red) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) s += partial[t];
+    return block_sum(s, red);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_init(LzDev *lz, const double *partial, int n,
+                                                      double *sigma, double *cprev,
+                                                      double tol) {
+    __shared__ double red[16];
+    const double s = fixed_sum(partial, n, red);
+    if (threadIdx.x == 0) {
+        lz->stopped = 0;
+        lz->tol = tol;
+        lz->scale = 0.0;
+        lz->norm0 = sqrt(s);
+        lz->bad_start = !(s > 0.0);
+        lz->psi_norm = 0.0;
+        sigma[0] = 1.0;
+        cprev[0] = 0.0;
+        if (lz->bad_start) lz->stopped = -1;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void init_write(const double *__restrict__ v0,
+                                                     T *__restrict__ r, int64_t n,
+                                                     const LzDev *__restrict__ lz) {
+    if (lz->stopped) return;
+    const double inv = 1.0 / lz->norm0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = (T)(v0[i] * inv);
+}
+
+__global__ __launch_bounds__(kBlock) void finish_alpha(LzDev *lz, const double *partial,
+                                                       int n, double *alpha, int k) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    const double s = fixed_sum(partial, n, red);
+    if (threadIdx.x == 0) alpha[k] = s;
+}
+
+// w -= alpha_k sigma_k r_k (FP64 arithmetic, one rounding), partial |w|^2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pass_b(T *__restrict__ w, const T *__restrict__ r,
+                                                 int64_t n, const LzDev *__restrict__ lz,
+                                                 const double *__restrict__ alpha,
+                                                 const double *__restrict__ sigma, int k,
+                                                 double *__restrict__ partial) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    const double a = alpha[k] * sigma[k];
+    int64_t first, last;
+    block_rows<int64_t>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, n, first, last);
+    double s = 0.0;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+        const T wi = (T)((double)w[i] - a * (double)r[i]);
+        w[i] = wi;
+        s += (double)wi * (double)wi;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void finish_beta(LzDev *lz, const double *partial, int n,
+                                                      const double *alpha, double *beta,
+                                                      double *sigma, double *cprev, int k) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    const double s = fixed_sum(partial, n, red);
+    if (threadIdx.x == 0) {
+        const double b = sqrt(s);
+        beta[k] = b;
+        const double sc = fmax(lz->scale, fmax(fabs(alpha[k]), b));
+        lz->scale = sc;
+        if (!(b > lz->tol * sc)) {
+            lz->stopped = k + 1;
+        } else {
+            sigma[k + 1] = 1.0 / b;
+            cprev[k + 1] = b * sigma[k];
+        }
+    }
+}
+
+// Reorthogonalization: partial[j * G + blk] = sum_i V[j][i] w_i over the slice.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reorth_dots(const T *__restrict__ V,
+                                                      const T *__restrict__ w, int64_t n,
+                                                      int nv, double *__restrict__ partial,
+                                                      const LzDev *__restrict__ lz) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    const int j = blockIdx.y;
+    int64_t first, last;
+    block_rows<int64_t>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, n, first, last);
+    double s = 0.0;
+    const T *Vj = V + (size_t)j * (size_t)n;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x)
+        s += (double)Vj[i] * (double)w[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void reorth_finish(const double *partial, int G, int nv,
+                                                        double *h, const LzDev *lz) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    for (int j = 0; j < nv; ++j) {
+        const double s = fixed_sum(partial + (size_t)j * G, G, red);
+        if (threadIdx.x == 0) h[j] = s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reorth_update(const T *__restrict__ V,
+                                                        T *__restrict__ w, int64_t n, int nv,
+                                                        const double *__restrict__ h,
+                                                        const LzDev *__restrict__ lz) {
+    if (lz->stopped) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = (double)w[i];
+        for (int j = 0; j < nv; ++j) acc -= h[j] * (double)V[(size_t)j * (size_t)n + i];
+        w[i] = (T)acc;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void finish_psi_norm(LzDev *lz, const double *partial,
+                                                          int n) {
+    __shared__ double red[16];
+    const double s = fixed_sum(partial, n, red);
+    if (threadIdx.x == 0) lz->psi_norm = sqrt(s);
+}
+
+__global__ __launch_bounds__(kBlock) void scale_psi(double *__restrict__ psi, int64_t n,
+                                                    const LzDev *__restrict__ lz) {
+    const double nrm = lz->psi_norm;
+    if (!(nrm > 0.0)) return;
+    const double inv = 1.0 / nrm;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        psi[i] *= inv;
+}
+
+// Ground-state accumulation psi += c_k v_k = c_k sigma_k r_k in FP64.  Kept out
+// of the H x kernel so both Lanczos passes run the same recurrence kernels.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void psi_axpy(double *__restrict__ psi,
+                                                   const T *__restrict__ r, int64_t n,
+                                                   const double *__restrict__ coef,
+                                                   const double *__restrict__ sigma,
+                                                   const LzDev *__restrict__ lz) {
+    if (lz->stopped) return;
+    const double a = coef[0] * sigma[0];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        psi[i] += a * (double)r[i];
+}
+
+__global__ void zero_f64(double *__restrict__ x, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+static thread_local bool g_timing = false;
+static thread_local double g_hx_ms = 0.0, g_loop_ms = 0.0;
+static thread_local int g_hx_launches = 0;
+
+struct Run {
+    Basis *b;
+    const Couplings *c;
+    int steps, prec, reorth, kernel, use_graph;
+    double tol;
+    Layout L;
+    unsigned char *w;
+    hipStream_t st;
+    const double *v0;
+    const double *coef_host;   // ritz pass: c_k (host), else nullptr
+    double *psi;               // ritz pass output, else nullptr
+};
+
+template <typename T>
+static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
+    Basis *b = R.b;
+    const int64_t n = b->dim;
+    LzDev *lz = (LzDev *)(R.w + R.L.lz);
+    double *alpha = (double *)(R.w + R.L.alpha), *beta = (double *)(R.w + R.L.beta);
+    double *sigma = (double *)(R.w + R.L.sigma), *cprev = (double *)(R.w + R.L.cprev);
+    double *coef = (double *)(R.w + R.L.coef), *hc = (double *)(R.w + R.L.hcoef);
+    double *partial = (double *)(R.w + R.L.partial);
+    T *buf[3] = {(T *)(R.w + R.L.r0), (T *)(R.w + R.L.r1), (T *)(R.w + R.L.r2)};
+    T *V = (T *)(R.w + R.L.V);
+    const int G = R.L.grid_vec;
+    const int Ghx = hx_partial_count(b, R.kernel);
+    const int dtype = R.prec == HM_PREC_F64 ? HM_F64 : HM_F32;
+    for (int k = k0; k < k1; ++k) {
+        T *rk = buf[k % 3], *rprev = buf[(k + 2) % 3], *wn = buf[(k + 1) % 3];
+        HxPass p;
+        p.x = rk;
+        p.y = wn;
+        p.p = k > 0 ? rprev : nullptr;
+        p.sigma = sigma + k;
+        p.cprev = cprev + k;
+        p.partial = partial;
+        p.store = R.reorth ? (void *)(V + (size_t)k * (size_t)n) : nullptr;
+        p.stopped = &lz->stopped;
+        if (ev) HM_HIP(hipEventRecord((*ev)[2 * k], R.st));
+        HM_TRY(launch_hx(b, R.c, dtype, R.kernel, p, R.st));
+        if (ev) HM_HIP(hipEventRecord((*ev)[2 * k + 1], R.st));
+        if (R.psi)
+            hipLaunchKernelGGL(psi_axpy<T>, dim3(G), dim3(kBlock), 0, R.st, R.psi, rk, n,
+                               coef + k, sigma + k, lz);
+        hipLaunchKernelGGL(finish_alpha, dim3(1), dim3(kBlock), 0, R.st, lz, partial, Ghx,
+                           alpha, k);
+        hipLaunchKernelGGL(pass_b<T>, dim3(G), dim3(kBlock), 0, R.st, wn, rk, n, lz, alpha,
+                           sigma, k, partial);
+        if (R.reorth) {
+            for (int rep = 0; rep < 2; ++rep) {
+                hipLaunchKernelGGL(reorth_dots<T>, dim3(G, k + 1), dim3(kBlock), 0, R.st, V,
+                                   wn, n, k + 1, partial, lz);
+                hipLaunchKernelGGL(reorth_finish, dim3(1), dim3(kBlock), 0, R.st, partial, G,
+                                   k + 1, hc, lz);
+                hipLaunchKernelGGL(reorth_update<T>, dim3(G), dim3(kBlock), 0, R.st, V, wn, n,
+                                   k + 1, hc, lz);
+            }
+            hipLaunchKernelGGL(sumsq_kernel<T>, dim3(G), dim3(kBlock), 0, R.st, wn, n, partial,
+                               &lz->stopped);
+        }
+        hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G, alpha,
+                           beta, sigma, cprev, k);
+    }
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+}
+
+template <typename T>
+static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done) {
+    Basis *b = R.b;
+    const int64_t n = b->dim;
+    LzDev *lz = (LzDev *)(R.w + R.L.lz);
+    double *partial = (double *)(R.w + R.L.partial);
+    double *sigma = (double *)(R.w + R.L.sigma), *cprev = (double *)(R.w + R.L.cprev);
+    T *r0 = (T *)(R.w + R.L.r0);
+    const int G = R.L.grid_vec;
+    if (R.psi) {
+        HM_HIP(hipMemcpyAsync(R.w + R.L.coef, R.coef_host, sizeof(double) * R.steps,
+                              hipMemcpyHostToDevice, R.st));
+        hipLaunchKernelGGL(zero_f64, dim3(G), dim3(kBlock), 0, R.st, R.psi, n);
+    }
+    hipLaunchKernelGGL(sumsq_kernel<double>, dim3(G), dim3(kBlock), 0, R.st, R.v0, n, partial,
+                       (const int *)nullptr);
+    hipLaunchKernelGGL(finish_init, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G, sigma,
+                       cprev, R.tol);
+    hipLaunchKernelGGL(init_write<T>, dim3(G), dim3(kBlock), 0, R.st, R.v0, r0, n, lz);
+    HM_HIP(hipGetLastError());
+
+    const bool timing = g_timing;
+    std::vector<hipEvent_t> ev;
+    hipEvent_t lo = nullptr, hi = nullptr;
+    if (timing) {
+        ev.resize(2 * (size_t)R.steps);
+        for (auto &e : ev) HM_HIP(hipEventCreate(&e));
+        HM_HIP(hipEventCreate(&lo));
+        HM_HIP(hipEventCreate(&hi));
+        HM_HIP(hipEventRecord(lo, R.st));
+    }
+    int rc = HM_OK;
+    if (R.use_graph && !timing) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HM_HIP(hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_steps<T>(R, 0, R.steps, nullptr);
+        hipError_t e = hipStreamEndCapture(R.st, &graph);
+        if (rc != HM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(HM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, R.st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(HM_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+    } else {
+        rc = enqueue_steps<T>(R, 0, R.steps, timing ? &ev : nullptr);
+        if (rc != HM_OK) return rc;
+    }
+    if (R.psi) {
+        hipLaunchKernelGGL(sumsq_kernel<double>, dim3(G), dim3(kBlock), 0, R.st, R.psi, n,
+                           partial, (const int *)nullptr);
+        hipLaunchKernelGGL(finish_psi_norm, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G);
+        hipLaunchKernelGGL(scale_psi, dim3(G), dim3(kBlock), 0, R.st, R.psi, n, lz);
+    }
+    if (timing) HM_HIP(hipEventRecord(hi, R.st));
+    HM_HIP(hipGetLastError());
+    HM_HIP(hipStreamSynchronize(R.st));
+
+    LzDev hlz;
+    HM_HIP(hipMemcpy(&hlz, lz, sizeof hlz, hipMemcpyDeviceToHost));
+    if (hlz.bad_start) return fail(HM_EINVAL, "start vector has zero norm");
+    const int done = hlz.stopped > 0 ? hlz.stopped : R.steps;
+    if (alpha_h)
+        HM_HIP(hipMemcpy(alpha_h, R.w + R.L.alpha, sizeof(double) * done, hipMemcpyDeviceToHost));
+    if (beta_h)
+        HM_HIP(hipMemcpy(beta_h, R.w + R.L.beta, sizeof(double) * done, hipMemcpyDeviceToHost));
+    if (alpha_h) std::fill(alpha_h + done, alpha_h + R.steps, 0.0);
+    if (beta_h) std::fill(beta_h + done, beta_h + R.steps, 0.0);
+    *steps_done = done;
+    if (timing) {
+        double hx = 0.0;
+        for (int k = 0; k < done; ++k) {
+            float ms = 0.f;
+            HM_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+            hx += ms;
+        }
+        float loop = 0.f;
+        HM_HIP(hipEventElapsedTime(&loop, lo, hi));
+        g_hx_ms = hx;
+        g_hx_launches = done;
+        g_loop_ms = loop;
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        (void)hipEventDestroy(lo);
+        (void)hipEventDestroy(hi);
+    }
+    return HM_OK;
+}
+
+static int check_opts(const Basis *b, const hm_lanczos_opts *o, int *kernel) {
+    if (!o) return fail(HM_EINVAL, "opts is null");
+    if (o->precision != HM_PREC_F64 && o->precision != HM_PREC_F32_MIXED)
+        return fail(HM_EINVAL, "unknown precision %d", o->precision);
+    if (o->kernel < 0 || o->kernel > 2) return fail(HM_EINVAL, "unknown kernel %d", o->kernel);
+    *kernel = choose_kernel(b, o->kernel);
+    if (*kernel < 0) return fail(HM_EINVAL, "spin-1/2 block kernel not applicable to this basis");
+    return HM_OK;
+}
+
+static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t steps,
+                      const hm_lanczos_opts *o, void *d_work, size_t work_bytes,
+                      const double *coef, double *d_psi, double *alpha, double *beta,
+                      int32_t *steps_done, void *stream) {
+    if (!h || !d_v0 || !d_work || !steps_done) return fail(HM_EINVAL, "null argument");
+    if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
+    Basis *b = &h->impl;
+    int kernel = 0;
+    HM_TRY(check_opts(b, o, &kernel));
+    const Couplings *c = nullptr;
+    HM_TRY(get_couplings(b, J, &c));
+    Run R{};
+    R.b = b;
+    R.c = c;
+    R.steps = steps;
+    R.prec = o->precision;
+    R.reorth = o->full_reorth ? 1 : 0;
+    R.kernel = kernel;
+    R.use_graph = o->use_graph ? 1 : 0;
+    R.tol = o->breakdown_tol > 0 ? o->breakdown_tol : 1e-12;
+    R.L = layout(b, steps, R.prec, R.reorth, kernel);
+    if (work_bytes < R.L.total)
+        return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, R.L.total);
+    R.w = (unsigned char *)d_work;
+    R.v0 = d_v0;
+    R.coef_host = coef;
+    R.psi = d_psi;
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (R.use_graph && st == nullptr) {
+        // the null stream cannot be captured; a blocking stream orders
+        // itself after earlier null-stream work
+        HM_HIP(hipStreamCreate(&own));
+        st = own;
+    }
+    R.st = st;
+    int done = 0;
+    int rc = R.prec == HM_PREC_F64 ? run_lanczos<double>(R, alpha, beta, &done)
+                                   : run_lanczos<float>(R, alpha, beta, &done);
+    if (own) (void)hipStreamDestroy(own);
+    if (rc != HM_OK) return rc;
+    *steps_done = done;
+    return HM_OK;
+}
+
+// Lowest eigenvalue of the symmetric tridiagonal T by bisection on the Sturm
+// count, then its eigenvector by inverse iteration.
+static int sturm_count(int k, const double *a, const double *b, double x) {
+    int neg = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+        const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++neg;
+    }
+    return neg;
+}
+
+static double lowest_eigenvalue(int k, const double *a, const double *b) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    const double span = std::max(std::fabs(lo), std::fabs(hi));
+    lo -= 1e-12 * span + 1e-300;
+    hi += 1e-12 * span + 1e-300;
+    for (int it = 0; it < 2000; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(k, a, b, mid) >= 1) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static void inverse_iteration(int k, const double *a, const double *b, double lam,
+                              double *x) {
+    // LU of (T - lam I) with partial pivoting for a tridiagonal matrix.
+    double norm = 0.0;
+    for (int i = 0; i < k; ++i)
+        norm = std::max(norm, std::fabs(a[i]) + (i > 0 ? std::fabs(b[i - 1]) : 0.0) +
+                                  (i + 1 < k ? std::fabs(b[i]) : 0.0));
+    const double tiny = std::max(norm, 1e-300) * 1e-15;
+    std::vector<double> d(k), du(k), du2(k), dl(k);
+    std::vector<int> piv(k);
+    for (int i = 0; i < k; ++i) {
+        d[i] = a[i] - lam;
+        du[i] = i + 1 < k ? b[i] : 0.0;
+        dl[i] = i + 1 < k ? b[i] : 0.0;
+        du2[i] = 0.0;
+    }
+    for (int i = 0; i + 1 < k; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+            piv[i] = 0;
+            if (d[i] == 0.0) d[i] = tiny;
+            const double f = dl[i] / d[i];
+            dl[i] = f;
+            d[i + 1] -= f * du[i];
+        } else {
+            piv[i] = 1;
+            const double f = d[i] / dl[i];
+            d[i] = dl[i];
+            dl[i] = f;
+            const double t = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = t - f * d[i + 1];
+            if (i + 2 < k) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -f * du[i + 1];
+            }
+        }
+    }
+    for (int i = 0; i < k; ++i)
+        if (std::fabs(d[i]) < tiny) d[i] = d[i] < 0 ? -tiny : tiny;
+    for (int i = 0; i < k; ++i) x[i] = 1.0 / std::sqrt((double)k) * (1.0 + 0.01 * ((i * 7919) % 13));
+    for (int rep = 0; rep < 3; ++rep) {
+        // forward: apply L^{-1} with the recorded row swaps
+        for (int i = 0; i + 1 < k; ++i) {
+            if (piv[i] == 0) {
+                x[i + 1] -= dl[i] * x[i];
+            } else {
+                const double t = x[i];
+                x[i] = x[i + 1];
+                x[i + 1] = t - dl[i] * x[i + 1];
+            }
+        }
+        // backward: U x = y
+        for (int i = k - 1; i >= 0; --i) {
+            double s = x[i];
+            if (i + 1 < k) s -= du[i] * x[i + 1];
+            if (i + 2 < k) s -= du2[i] * x[i + 2];
+            x[i] = s / d[i];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += x[i] * x[i];
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < k; ++i) x[i] /= nrm;
+    }
+    int first = 0;
+    while (first < k && std::fabs(x[first]) < 1e-300) ++first;
+    if (first < k && x[first] < 0)
+        for (int i = 0; i < k; ++i) x[i] = -x[i];
+}
+
+}  // namespace hm
+
+using hm::fail;
+
+extern "C" {
+
+int hm_tridiag_lowest(int32_t k, const double *alpha, const double *beta, double *eval,
+                      double *evec) {
+    hm::clear_error();
+    if (k < 1 || !alpha || !eval || (k > 1 && !beta)) return fail(HM_EINVAL, "bad arguments");
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(alpha[i]) || (i + 1 < k && !std::isfinite(beta[i])))
+            return fail(HM_EINVAL, "non-finite tridiagonal entry");
+    const double lam = hm::lowest_eigenvalue(k, alpha, beta);
+    *eval = lam;
+    if (evec) {
+        if (k == 1) evec[0] = 1.0;
+        else hm::inverse_iteration(k, alpha, beta, lam, evec);
+    }
+    return HM_OK;
+}
+
+int hm_lanczos_workspace(hm_basis h, int32_t steps, const hm_lanczos_opts *o, size_t *bytes) {
+    hm::clear_error();
+    if (!h || !bytes) return fail(HM_EINVAL, "null argument");
+    if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
+    int kernel = 0;
+    HM_TRY(hm::check_opts(&h->impl, o, &kernel));
+    *bytes = hm::layout(&h->impl, steps, o->precision, o->full_reorth ? 1 : 0, kernel).total;
+    return HM_OK;
+}
+
+int hm_lanczos(hm_basis h, const double *J, const double *d_v0, int32_t steps,
+               const hm_lanczos_opts *o, void *d_work, size_t work_bytes, double *alpha,
+               double *beta, double *E0, int32_t *steps_done, void *stream) {
+    hm::clear_error();
+    if (!alpha || !beta || !E0) return fail(HM_EINVAL, "null output");
+    int done = 0;
+    HM_TRY(hm::run_common(h, J, d_v0, steps, o, d_work, work_bytes, nullptr, nullptr, alpha,
+                          beta, &done, stream));
+    *steps_done = done;
+    return hm_tridiag_lowest(done, alpha, beta, E0, nullptr);
+}
+
+int hm_lanczos_ritz(hm_basis h, const double *J, const double *d_v0, int32_t steps_done,
+                    const double *c, const hm_lanczos_opts *o, void *d_work,
+                    size_t work_bytes, double *d_psi, double *alpha_out, double *beta_out,
+                    void *stream) {
+    hm::clear_error();
+    if (!c || !d_psi) return fail(HM_EINVAL, "null argument");
+    int done = 0;
+    HM_TRY(hm::run_common(h, J, d_v0, steps_done, o, d_work, work_bytes, c, d_psi, alpha_out,
+                          beta_out, &done, stream));
+    if (done != steps_done)
+        return fail(HM_EINVAL, "recompute stopped after %d of %d steps", done, steps_done);
+    return HM_OK;
+}
+
+int hm_set_timing(int32_t enable) {
+    hm::g_timing = enable != 0;
+    return HM_OK;
+}
+
+int hm_last_timing(double *hx_ms, int32_t *hx_launches, double *loop_ms) {
+    if (hx_ms) *hx_ms = hm::g_hx_ms;
+    if (hx_launches) *hx_launches = hm::g_hx_launches;
+    if (loop_ms) *loop_ms = hm::g_loop_ms;
+    return HM_OK;
+}
+
+}  // extern "C"
