@@ -95,6 +95,19 @@ int hm_basis_dim(hm_basis h, int64_t *dim);
 int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
                   int32_t *bits_per_digit);
 
+/* Schedule of the spin-1/2 block kernel (see hm_apply_kernel): the number of
+ * low sites K whose words are decoded and encoded through LDS tables (rows
+ * sharing the other N-K sites form one contiguous block), the threads per
+ * workgroup, and the rows each lane carries (rows with one low word and
+ * different high words, sharing the low-word work).  0 keeps the default
+ * (K = min(N, 12) for N <= 30, else 14; 256 threads; 4 rows per lane when
+ * dim >= 2^22, else 1).  Must be called before the first device use of the
+ * handle.  HM_EINVAL: K outside 1..min(14, N) or N - K > 24, block_threads
+ * not 64/128/256, rows_per_lane not 1/2/4/8, or tables already built.  Used
+ * by the autotuner. */
+int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
+                          int32_t rows_per_lane);
+
 /* ---------------------------------------------------------------------------
  * Decoding i -> |a_1..a_N> (Sec. 3.1) and encoding |a> -> i (Sec. 3.2) on the
  * host.  digits is a host array of N bytes, digits[u] = a_{u+1}.

@@ -89,6 +89,11 @@ class Basis:
     def handle(self):
         return self._h
 
+    def set_schedule(self, low_bits: int = 0, block_threads: int = 0, rows_per_lane: int = 0):
+        """Schedule of the spin-1/2 block kernel (before first device use)."""
+        check(lib().hm_basis_set_schedule(self._h, int(low_bits), int(block_threads),
+                                          int(rows_per_lane)))
+
     # --- codec ------------------------------------------------------------
     def unrank(self, i: int) -> np.ndarray:
         d = (ctypes.c_uint8 * self.N)()

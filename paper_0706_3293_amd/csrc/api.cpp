@@ -54,7 +54,7 @@ int hm_apply(hm_basis h, const double *J, const void *d_x, void *d_y, int32_t dt
     hm::HxPass p;
     p.x = d_x;
     p.y = d_y;
-    return hm::launch_hx(b, c, dtype, hm::choose_kernel(b, 0), p, (hipStream_t)stream);
+    return hm::launch_hx(b, c, dtype, hm::choose_kernel(b, c, 0), p, (hipStream_t)stream);
 }
 
 // Variant of hm_apply that forces one H x kernel (1: generic digits, 2: the
@@ -66,11 +66,11 @@ int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y, int
     if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_EINVAL, "unknown dtype %d", dtype);
     if (d_x == d_y) return fail(HM_EINVAL, "x and y must not alias");
     hm::Basis *b = &h->impl;
-    const int k = hm::choose_kernel(b, kernel);
-    if (k < 0 || kernel < 1 || kernel > 2)
-        return fail(HM_EINVAL, "kernel %d not applicable", kernel);
+    if (kernel < 1 || kernel > 2) return fail(HM_EINVAL, "kernel must be 1 or 2");
     const hm::Couplings *c = nullptr;
     HM_TRY(hm::get_couplings(b, J, &c));
+    const int k = hm::choose_kernel(b, c, kernel);
+    if (k < 0) return fail(HM_EINVAL, "kernel %d not applicable", kernel);
     hm::HxPass p;
     p.x = d_x;
     p.y = d_y;

@@ -29,8 +29,7 @@ Basis::~Basis() {
     // Handles are freed after their work completed (documented contract).
     if (d_prefix) (void)hipFree(d_prefix);
     if (d_ladder) (void)hipFree(d_ladder);
-    for (auto &kv : couplings)
-        if (kv.second->dev) (void)hipFree(kv.second->dev);
+    couplings.clear();   // each Couplings frees its device arrays
     if (half_tables && half_tables_free) half_tables_free(half_tables);
 }
 
@@ -277,6 +276,27 @@ int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
     if (two_s) *two_s = h->impl.two_s;
     if (A) *A = h->impl.A;
     if (bits_per_digit) *bits_per_digit = h->impl.bits;
+    return HM_OK;
+}
+
+int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
+                          int32_t rows_per_lane) {
+    hm::clear_error();
+    if (!h) return fail(HM_EINVAL, "null handle");
+    hm::Basis &b = h->impl;
+    std::lock_guard<std::mutex> lock(b.mu);
+    if (b.half_tables) return fail(HM_EINVAL, "schedule must be set before the first device use");
+    if (low_bits != 0 && (low_bits < 1 || low_bits > 14 || low_bits > b.N || b.N - low_bits > 24))
+        return fail(HM_EINVAL, "low_bits %d outside 1..min(14, N) with N - low_bits <= 24",
+                    low_bits);
+    if (block_threads != 0 && block_threads != 64 && block_threads != 128 && block_threads != 256)
+        return fail(HM_EINVAL, "block_threads must be 64, 128 or 256");
+    if (rows_per_lane != 0 && rows_per_lane != 1 && rows_per_lane != 2 && rows_per_lane != 4 &&
+        rows_per_lane != 8)
+        return fail(HM_EINVAL, "rows_per_lane must be 1, 2, 4 or 8");
+    b.half_K = low_bits;
+    b.half_block = block_threads;
+    b.half_R = rows_per_lane;
     return HM_OK;
 }
 

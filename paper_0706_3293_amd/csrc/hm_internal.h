@@ -51,6 +51,13 @@ struct Couplings {
     std::vector<BondDev> host;
     BondDev *dev = nullptr;   // nb entries (nullptr when nb == 0)
     double diag_shift = 0.0;  // sum_b mJ4 (used by the spin-1/2 kernel)
+    // bonds regrouped for the spin-1/2 block kernel (built on first use)
+    void *half = nullptr;
+    void (*half_free)(void *) = nullptr;
+    ~Couplings() {
+        if (dev) (void)hipFree(dev);
+        if (half && half_free) half_free(half);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -84,7 +91,10 @@ struct Basis {
     void *d_prefix = nullptr;           // uint32 or uint64 copy of prefix
     double *d_ladder = nullptr;
     std::map<std::vector<double>, std::unique_ptr<Couplings>> couplings;
-    // spin-1/2 block kernel tables (created on first use)
+    // spin-1/2 block kernel: schedule (0 = default) and tables (first use)
+    int half_K = 0;          // low bits per block word
+    int half_block = 0;      // threads per workgroup (64, 128 or 256)
+    int half_R = 0;          // rows per lane (high words sharing one low word)
     void *half_tables = nullptr;
     void (*half_tables_free)(void *) = nullptr;
 
@@ -128,7 +138,7 @@ struct HxPass {
 int hx_partial_count(const Basis *b, int kernel);      // partial slots needed
 int launch_hx(const Basis *b, const Couplings *c, int dtype, int kernel,
               const HxPass &pass, hipStream_t st);
-int choose_kernel(const Basis *b, int requested);
+int choose_kernel(const Basis *b, const Couplings *c, int requested);
 
 // Bond correlations.
 int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb,

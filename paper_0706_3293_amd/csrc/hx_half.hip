@@ -1,15 +1,631 @@
-// Spin-1/2 block kernel for H x (placeholder until the block kernel lands).
+// Spin-1/2 block kernel for the row-gather H x (Sec. 4, Eq. (E-4-b)).
+//
+// For s = 1/2 a basis state is an N-bit word with A set bits (a_u = 1 on the
+// set bits), and the order of Eq. (E-3-a) restricted to H(M) is the order of
+// the words' values.  The encoding sum of Sec. 3.2 then reduces to
+// sum_t C(c_t, t) over the set-bit positions c_1 < c_2 < ... (P[k][A_k][1] =
+// D(k-1, A_k) = C(k-1, A_k)).  Split a word into its low K bits L and high
+// N-K bits h: the index is Off(h) + rankL(L), where rankL is the position of L
+// among the K-bit words with the same number of set bits, and Off(h) depends
+// on h only.  So the rows with one high part h form a contiguous block of
+// C(K, A - popcount(h)) rows, ordered like the low words.
+//
+// Work item = (a group of R high words with the same popcount, a chunk of 64
+// low words of their class).  Lane r owns the low word L of rank r and the R
+// rows (h_m, L), m = 0..R-1:
+//   * bonds inside the low word: flip test and rankL(L') (LDS table) are done
+//     once per lane and reused for the R rows; target Off(h_m) + rankL(L');
+//   * bonds inside the high word: flip and target block are the same for the
+//     whole wavefront and the low word is unchanged, so the 64 lanes gather 64
+//     consecutive entries of x at Off(h_m') + r: coalesced;
+//   * bonds with one site in each word: the high bit is wave-uniform, the low
+//     bit decides per lane, target Off(h_m') + rankL(L').
+// Target block offsets of the high and straddling bonds depend on h and the
+// bond only; they are tabulated per (basis, couplings).
+// y_i = shift x_i + sum over flippable bonds of (-J/2)(x_j - x_i), with
+// shift = -sum_b J_b / 4 (s = 1/2: m_u m_v = +-1/4 and every allowed ladder
+// term has matrix element -J/2).  A bond that cannot flip gathers x_i itself
+// and so adds zero; this keeps eight gathers in flight without branches.
+// Each row is written by one lane; workgroups are persistent and each XCD
+// sweeps one contiguous slice of the items.
+#include <algorithm>
+#include <vector>
+
 #include "device_common.h"
 #include "hm_internal.h"
 
 namespace hm {
 
-bool half_supported(const Basis *) { return false; }
+constexpr int kHalfMaxK = 14;
+constexpr int kHalfMaxHighBits = 24;
+constexpr int kGroup = 8;
+constexpr uint32_t kNoHigh = 0xFFFFFFFFu;      // padding slot of a high-word group
+constexpr size_t kMaxNeighbourBytes = (size_t)1 << 30;
 
-int hx_half_grid(const Basis *) { return 1; }
+// Eight bonds of one group, structure-of-arrays so one group is fetched with
+// a few wide scalar loads.
+//   low group:        m1 = bits u, v of the low word
+//   high group:       m1 = bits u-K, v-K of the high word
+//   straddling group: m1 = bit u of the low word, m2 = bit v-K of the high word
+// Padding entries have m1 = m2 = 0 and coefficient 0; they never flip.
+struct BondGroup {
+    uint32_t m1[kGroup];
+    uint32_t m2[kGroup];
+    float c32[kGroup];      // -J/2 rounded to FP32
+    uint32_t pad[kGroup];
+    double c64[kGroup];     // -J/2
+};
 
-int launch_hx_half(const Basis *, const Couplings *, int, const HxPass &, hipStream_t) {
-    return fail(HM_EINVAL, "spin-1/2 block kernel not available");
+// Per-basis tables of the block kernel.
+struct HalfTables {
+    int K = 0, block = 256, R = 1;
+    int64_t n_items = 0, n_groups = 0;
+    std::vector<uint64_t> off_host;
+    uint16_t *d_rankL = nullptr, *d_unrankL = nullptr;
+    void *d_off = nullptr;            // uint32 or uint64 per high word
+    uint32_t *d_hgroups = nullptr;    // n_groups x R high words
+    uint32_t *d_items = nullptr;      // (group << 8) | chunk
+    int class_start[kHalfMaxK + 2] = {0};
+    int class_size[kHalfMaxK + 2] = {0};
+};
+
+static void free_half(void *p) {
+    auto *t = (HalfTables *)p;
+    if (!t) return;
+    if (t->d_rankL) (void)hipFree(t->d_rankL);
+    if (t->d_unrankL) (void)hipFree(t->d_unrankL);
+    if (t->d_off) (void)hipFree(t->d_off);
+    if (t->d_hgroups) (void)hipFree(t->d_hgroups);
+    if (t->d_items) (void)hipFree(t->d_items);
+    delete t;
+}
+
+// Bonds of one coupling list regrouped for a given K, plus the neighbour
+// table: for every high word h, (nHg + nSg) * 8 block offsets, in group
+// order (cached in the Couplings object of the basis).
+struct HalfBonds {
+    int K = -1, nLg = 0, nHg = 0, nSg = 0;
+    BondGroup *groups = nullptr;
+    void *nbr = nullptr;
+};
+
+template <typename I>
+struct HalfArgs {
+    const uint16_t *rankL, *unrankL;
+    const I *off;
+    const I *nbr;
+    const uint32_t *hgroups;
+    const uint32_t *items;
+    const BondGroup *groups;
+    uint32_t n_items;
+    int K, A, nLg, nHg, nSg, width;
+    double shift;
+    int class_start[kHalfMaxK + 2];
+    int class_size[kHalfMaxK + 2];
+};
+
+template <typename T> __device__ __forceinline__ T coef(const BondGroup &g, int q);
+template <> __device__ __forceinline__ float coef<float>(const BondGroup &g, int q) {
+    return g.c32[q];
+}
+template <> __device__ __forceinline__ double coef<double>(const BondGroup &g, int q) {
+    return g.c64[q];
+}
+
+template <typename T, typename I, int R, bool DOT, bool STORE>
+__global__ __launch_bounds__(256) void hx_half_kernel(
+    const HalfArgs<I> g, const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ prev,
+    const double *__restrict__ sigma_p, const double *__restrict__ cprev_p,
+    double *__restrict__ partial, T *__restrict__ store, const int *__restrict__ stopped) {
+    if (stopped && *stopped) return;
+    extern __shared__ __align__(16) uint16_t lds16[];
+    __shared__ double red[16];
+    const int nlow = 1 << g.K;
+    uint16_t *rankL = lds16;
+    uint16_t *unrankL = lds16 + nlow;
+    for (int t = threadIdx.x; t < nlow; t += blockDim.x) {
+        rankL[t] = g.rankL[t];
+        unrankL[t] = g.unrankL[t];
+    }
+    __syncthreads();
+
+    const double sigma = sigma_p ? *sigma_p : 1.0;
+    const double cprev = cprev_p ? *cprev_p : 0.0;
+    const T shift = (T)g.shift;
+    const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    // Item range of this wave: with a grid that is a multiple of 8, XCD
+    // (blockIdx % 8) owns the contiguous eighth [x n/8, (x+1) n/8) of the items
+    // and its waves stride through it together.
+    uint32_t first = 0, last = g.n_items, stride = gridDim.x * nw, wl;
+    if (gridDim.x % kXcds == 0) {
+        const uint32_t x8 = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+        first = (uint32_t)((uint64_t)g.n_items * x8 / kXcds);
+        last = (uint32_t)((uint64_t)g.n_items * (x8 + 1) / kXcds);
+        stride = per * nw;
+        wl = (blockIdx.x / kXcds) * nw + (threadIdx.x >> 6);
+    } else {
+        wl = blockIdx.x * nw + (threadIdx.x >> 6);
+    }
+    wl = __builtin_amdgcn_readfirstlane(wl);
+    first = __builtin_amdgcn_readfirstlane(first);
+    last = __builtin_amdgcn_readfirstlane(last);
+    stride = __builtin_amdgcn_readfirstlane(stride);
+    const BondGroup *__restrict__ gl = g.groups;
+    const BondGroup *__restrict__ gh = g.groups + g.nLg;
+    const BondGroup *__restrict__ gs = g.groups + g.nLg + g.nHg;
+    double dot = 0.0;
+    for (uint32_t it = first + wl; it < last; it += stride) {
+        const uint32_t item = g.items[it];
+        const uint32_t *__restrict__ hg = g.hgroups + (size_t)(item >> 8) * R;
+        uint32_t hs[R];
+        bool valid[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) hs[m] = hg[m];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            valid[m] = hs[m] != kNoHigh;
+            if (!valid[m]) hs[m] = hs[0];          // padding slots shadow slot 0
+        }
+        const int aL = g.A - __popc(hs[0]);
+        const int S = g.class_size[aL];
+        const int r0 = (int)(item & 255u) * 64 + lane;
+        const bool live = r0 < S;
+        const int r = live ? r0 : 0;              // dead lanes shadow row 0 of the block
+        const uint32_t L = unrankL[g.class_start[aL] + r];
+        I off[R];
+        const I *__restrict__ nb[R];
+        T xi[R], acc[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            off[m] = g.off[hs[m]];
+            nb[m] = g.nbr + (size_t)hs[m] * g.width;
+            xi[m] = x[off[m] + (I)r];
+            acc[m] = 0;
+        }
+        // bonds inside the low word: the test and rankL(L ^ m) once per lane
+        for (int k = 0; k < g.nLg; ++k) {
+            const BondGroup &G = gl[k];
+            uint32_t mk[kGroup], idx[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) mk[q] = G.m1[q];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) idx[q] = rankL[L ^ mk[q]];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q)
+                idx[q] = __popc(L & mk[q]) == 1 ? idx[q] : (uint32_t)r;
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const T *__restrict__ xb = x + off[m];
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) xj[q] = xb[idx[q]];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+            }
+        }
+        // bonds inside the high word: tabulated target block (own block if
+        // the bond cannot flip), same low word
+        for (int k = 0; k < g.nHg; ++k) {
+            const BondGroup &G = gh[k];
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    const T *__restrict__ xo = x + nb[m][k * kGroup + q];
+                    xj[q] = xo[(uint32_t)r];
+                }
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+            }
+        }
+        // bonds with one site in each word: uniform high bit, per-lane low bit
+        for (int k = 0; k < g.nSg; ++k) {
+            const BondGroup &G = gs[k];
+            uint32_t ml[kGroup], lb[kGroup], rk[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) ml[q] = G.m1[q];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                rk[q] = rankL[L ^ ml[q]];
+                lb[q] = L & ml[q];
+            }
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const I *__restrict__ nbs = nb[m] + (g.nHg + k) * kGroup;
+                const I own = off[m] + (I)r;
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    // the low-bit value that differs from the high bit;
+                    // padding entries (ml = 0) get an impossible value
+                    const uint32_t want = ml[q] == 0 ? 1u : ((hs[m] & G.m2[q]) ? 0u : ml[q]);
+                    xj[q] = x[lb[q] == want ? nbs[q] + (I)rk[q] : own];
+                }
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            if (live && valid[m]) {
+                const I row = off[m] + (I)r;
+                const T hv = shift * xi[m] + acc[m];
+                double w = sigma * (double)hv;
+                if (prev) w -= cprev * (double)prev[row];
+                const T wt = (T)w;
+                y[row] = wt;
+                if constexpr (DOT) dot += (double)wt * (sigma * (double)xi[m]);
+                if constexpr (STORE) store[row] = (T)(sigma * (double)xi[m]);
+            }
+        }
+    }
+    if constexpr (DOT) {
+        const double s = block_sum(dot, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int default_low_bits(int N) {
+    int K = N <= 30 ? std::min(N, 12) : 14;
+    if (N - K > kHalfMaxHighBits) K = N - kHalfMaxHighBits;
+    return K;
+}
+
+static int low_bits_of(const Basis *b) { return b->half_K > 0 ? b->half_K : default_low_bits(b->N); }
+static int block_of(const Basis *b) { return b->half_block > 0 ? b->half_block : 256; }
+static int rows_of(const Basis *b) {
+    if (b->half_R > 0) return b->half_R;
+    return b->dim >= ((int64_t)1 << 22) ? 4 : 1;
+}
+
+bool half_supported(const Basis *b) {
+    if (b->two_s != 1) return false;
+    const int K = low_bits_of(b);
+    return K <= kHalfMaxK && K <= b->N && b->N - K <= kHalfMaxHighBits;
+}
+
+static int64_t binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// Number of (high-word group, 64-row chunk) items, from the block sizes.
+static int64_t item_count(const Basis *b) {
+    const int K = low_bits_of(b), nh = b->N - K, R = rows_of(b);
+    int64_t n = 0;
+    for (int ph = 0; ph <= nh; ++ph) {
+        const int aL = b->A - ph;
+        if (aL < 0 || aL > K) continue;
+        n += ((binom(nh, ph) + R - 1) / R) * ((binom(K, aL) + 63) / 64);
+    }
+    return n;
+}
+
+static int grid_for_items(int64_t n_items, int block) {
+    const int nw = block / 64;
+    int64_t g = (n_items + nw - 1) / nw;
+    g = std::min<int64_t>(g, kMaxGrid);
+    g = std::max<int64_t>(g, 1);
+    if (g >= kXcds) g -= g % kXcds;
+    return (int)g;
+}
+
+// Workgroups of the block kernel (= FP64 partial sums it writes).
+int hx_half_grid(const Basis *b) { return grid_for_items(item_count(b), block_of(b)); }
+
+static hipError_t upload(void **dst, const void *src, size_t bytes) {
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return e;
+}
+
+static int half_prepare(Basis *b, HalfTables **out) {
+    std::lock_guard<std::mutex> lock(b->mu);
+    HM_TRY(device_prepare(b));
+    if (b->half_tables) {
+        *out = (HalfTables *)b->half_tables;
+        return HM_OK;
+    }
+    const int N = b->N, A = b->A;
+    const int K = low_bits_of(b), R = rows_of(b);
+    if (K > kHalfMaxK || N - K > kHalfMaxHighBits || K < 1 || K > N)
+        return fail(HM_EINVAL, "block kernel: low bits K=%d unsupported for N=%d", K, N);
+    auto *t = new HalfTables;
+    t->K = K;
+    t->R = R;
+    t->block = block_of(b);
+    const int nlow = 1 << K;
+    std::vector<uint16_t> rankL(nlow), unrankL(nlow);
+    std::vector<int> fill(K + 1, 0);
+    for (int a = 0, s = 0; a <= K; ++a) {
+        t->class_start[a] = s;
+        t->class_size[a] = (int)binom(K, a);
+        s += t->class_size[a];
+    }
+    for (int L = 0; L < nlow; ++L) {   // ascending values: colex order per class
+        const int a = __builtin_popcount((unsigned)L);
+        rankL[L] = (uint16_t)fill[a];
+        unrankL[t->class_start[a] + fill[a]] = (uint16_t)L;
+        ++fill[a];
+    }
+    const int nh = N - K;
+    const int64_t nhigh = (int64_t)1 << nh;
+    t->off_host.assign(nhigh, 0);
+    std::vector<std::vector<uint32_t>> by_class(nh + 1);
+    int64_t expect = 0;
+    for (int64_t h = 0; h < nhigh; ++h) {
+        const int ph = __builtin_popcountll((unsigned long long)h);
+        const int aL = A - ph;
+        if (aL < 0 || aL > K) continue;
+        uint64_t o = 0;
+        int t_idx = aL;
+        for (int q = 0; q < nh; ++q)
+            if ((h >> q) & 1) o += (uint64_t)binom(K + q, ++t_idx);
+        if ((int64_t)o != expect) {
+            free_half(t);
+            return fail(HM_EINVAL, "internal: block offsets out of order at h=%lld", (long long)h);
+        }
+        t->off_host[h] = o;
+        expect += t->class_size[aL];
+        by_class[ph].push_back((uint32_t)h);
+    }
+    if (expect != b->dim) {
+        free_half(t);
+        return fail(HM_EINVAL, "internal: block sizes sum to %lld, dim %lld", (long long)expect,
+                    (long long)b->dim);
+    }
+    // groups of R high words of one popcount class, ordered by the offset of
+    // their first block so the sweep follows memory order
+    struct Grp { uint64_t key; int ph; size_t start; };
+    std::vector<Grp> grps;
+    for (int ph = 0; ph <= nh; ++ph)
+        for (size_t s = 0; s < by_class[ph].size(); s += R)
+            grps.push_back({t->off_host[by_class[ph][s]], ph, s});
+    std::sort(grps.begin(), grps.end(), [](const Grp &a, const Grp &b) { return a.key < b.key; });
+    std::vector<uint32_t> hgroups, items;
+    hgroups.reserve(grps.size() * R);
+    for (size_t gi = 0; gi < grps.size(); ++gi) {
+        const auto &cls = by_class[grps[gi].ph];
+        for (int m = 0; m < R; ++m) {
+            const size_t s = grps[gi].start + m;
+            hgroups.push_back(s < cls.size() ? cls[s] : kNoHigh);
+        }
+        const int S = t->class_size[A - grps[gi].ph];
+        for (int c = 0; c * 64 < S; ++c) items.push_back(((uint32_t)gi << 8) | (uint32_t)c);
+    }
+    if ((int64_t)items.size() != item_count(b) || grps.size() >= ((size_t)1 << 24)) {
+        free_half(t);
+        return fail(HM_EINVAL, "internal: %zu items, expected %lld", items.size(),
+                    (long long)item_count(b));
+    }
+    t->n_items = (int64_t)items.size();
+    t->n_groups = (int64_t)grps.size();
+    hipError_t e = upload((void **)&t->d_rankL, rankL.data(), nlow * sizeof(uint16_t));
+    if (e == hipSuccess) e = upload((void **)&t->d_unrankL, unrankL.data(), nlow * sizeof(uint16_t));
+    if (e == hipSuccess) {
+        if (b->idx32) {
+            std::vector<uint32_t> o32(t->off_host.begin(), t->off_host.end());
+            e = upload(&t->d_off, o32.data(), o32.size() * sizeof(uint32_t));
+        } else {
+            e = upload(&t->d_off, t->off_host.data(), t->off_host.size() * sizeof(uint64_t));
+        }
+    }
+    if (e == hipSuccess)
+        e = upload((void **)&t->d_hgroups, hgroups.data(), hgroups.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = upload((void **)&t->d_items, items.data(), items.size() * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        free_half(t);
+        return fail(HM_EDEVICE, "block kernel tables: %s", hipGetErrorString(e));
+    }
+    b->half_tables = t;
+    b->half_tables_free = free_half;
+    *out = t;
+    return HM_OK;
+}
+
+static void free_half_bonds(void *p) {
+    auto *hb = (HalfBonds *)p;
+    if (!hb) return;
+    if (hb->groups) (void)hipFree(hb->groups);
+    if (hb->nbr) (void)hipFree(hb->nbr);
+    delete hb;
+}
+
+struct Flat {
+    uint32_t m1 = 0, m2 = 0;
+    double c = 0.0;
+};
+
+static void to_groups(const std::vector<Flat> &v, std::vector<BondGroup> &out) {
+    for (size_t i = 0; i < v.size(); i += kGroup) {
+        BondGroup G{};
+        for (int q = 0; q < kGroup && i + q < v.size(); ++q) {
+            G.m1[q] = v[i + q].m1;
+            G.m2[q] = v[i + q].m2;
+            G.c64[q] = v[i + q].c;
+            G.c32[q] = (float)v[i + q].c;
+        }
+        out.push_back(G);
+    }
+}
+
+static size_t neighbour_bytes(const Basis *b, const Couplings *c, int K) {
+    int nH = 0, nS = 0;
+    for (const BondDev &bd : c->host) {
+        if (bd.u >= K) ++nH;
+        else if (bd.v >= K) ++nS;
+    }
+    const size_t width = (size_t)((nH + kGroup - 1) / kGroup + (nS + kGroup - 1) / kGroup) * kGroup;
+    return ((size_t)1 << (b->N - K)) * width * (b->idx32 ? 4 : 8);
+}
+
+static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
+                      const HalfBonds **out) {
+    const int K = t->K;
+    std::lock_guard<std::mutex> lock(b->mu);
+    auto *cc = const_cast<Couplings *>(c);
+    if (cc->half && ((HalfBonds *)cc->half)->K == K) {
+        *out = (const HalfBonds *)cc->half;
+        return HM_OK;
+    }
+    if (neighbour_bytes(b, c, K) > kMaxNeighbourBytes)
+        return fail(HM_ERANGE, "block kernel neighbour table would exceed %zu bytes",
+                    kMaxNeighbourBytes);
+    std::vector<Flat> lo, hi, st;
+    for (const BondDev &bd : c->host) {
+        Flat f;
+        f.c = bd.mJ2;
+        if (bd.v < K) {
+            f.m1 = (1u << bd.u) | (1u << bd.v);
+            lo.push_back(f);
+        } else if (bd.u >= K) {
+            f.m1 = (1u << (bd.u - K)) | (1u << (bd.v - K));
+            hi.push_back(f);
+        } else {
+            f.m1 = 1u << bd.u;
+            f.m2 = 1u << (bd.v - K);
+            st.push_back(f);
+        }
+    }
+    std::vector<BondGroup> groups;
+    to_groups(lo, groups);
+    const int nLg = (int)groups.size();
+    to_groups(hi, groups);
+    const int nHg = (int)groups.size() - nLg;
+    to_groups(st, groups);
+    const int nSg = (int)groups.size() - nLg - nHg;
+    const int width = (nHg + nSg) * kGroup;
+    const int64_t nhigh = (int64_t)1 << (b->N - K);
+    // neighbour table: high bonds -> Off(h ^ m) if the bond flips, else Off(h);
+    // straddling bonds -> Off(h ^ m2)
+    std::vector<uint64_t> nbr((size_t)nhigh * width, 0);
+    for (int64_t h = 0; h < nhigh; ++h) {
+        const int aL = b->A - __builtin_popcountll((unsigned long long)h);
+        if (aL < 0 || aL > K) continue;
+        uint64_t *row = &nbr[(size_t)h * width];
+        for (int k = 0; k < nHg; ++k)
+            for (int q = 0; q < kGroup; ++q) {
+                const uint32_t m = groups[nLg + k].m1[q];
+                const bool flips = __builtin_popcountll((unsigned long long)(h & m)) == 1;
+                row[k * kGroup + q] = t->off_host[flips ? (h ^ m) : h];
+            }
+        for (int k = 0; k < nSg; ++k)
+            for (int q = 0; q < kGroup; ++q)
+                row[(nHg + k) * kGroup + q] = t->off_host[h ^ groups[nLg + nHg + k].m2[q]];
+    }
+    auto *hb = new HalfBonds;
+    hb->K = K;
+    hb->nLg = nLg;
+    hb->nHg = nHg;
+    hb->nSg = nSg;
+    hipError_t e = hipSuccess;
+    if (!groups.empty()) e = upload((void **)&hb->groups, groups.data(), groups.size() * sizeof(BondGroup));
+    if (e == hipSuccess && !nbr.empty()) {
+        if (b->idx32) {
+            std::vector<uint32_t> n32(nbr.begin(), nbr.end());
+            e = upload(&hb->nbr, n32.data(), n32.size() * sizeof(uint32_t));
+        } else {
+            e = upload(&hb->nbr, nbr.data(), nbr.size() * sizeof(uint64_t));
+        }
+    }
+    if (e != hipSuccess) {
+        free_half_bonds(hb);
+        return fail(HM_EDEVICE, "block kernel bonds: %s", hipGetErrorString(e));
+    }
+    if (cc->half && cc->half_free) cc->half_free(cc->half);
+    cc->half = hb;
+    cc->half_free = free_half_bonds;
+    *out = hb;
+    return HM_OK;
+}
+
+template <typename T, typename I, int R>
+static void launch_r(const HalfTables *t, const HalfArgs<I> &g, const HxPass &p, hipStream_t st) {
+    const int grid = grid_for_items(t->n_items, t->block);
+    const size_t lds = 2 * sizeof(uint16_t) * ((size_t)1 << t->K);
+    const T *x = (const T *)p.x;
+    T *y = (T *)p.y;
+    const T *pr = (const T *)p.p;
+    T *store = (T *)p.store;
+#define HM_LAUNCH(D, S)                                                                     \
+    hipLaunchKernelGGL((hx_half_kernel<T, I, R, D, S>), dim3(grid), dim3(t->block), lds, st, \
+                       g, x, y, pr, p.sigma, p.cprev, p.partial, store, p.stopped)
+    const bool dot = p.partial != nullptr, sto = store != nullptr;
+    if (!dot && !sto) HM_LAUNCH(false, false);
+    else if (dot && !sto) HM_LAUNCH(true, false);
+    else if (!dot && sto) HM_LAUNCH(false, true);
+    else HM_LAUNCH(true, true);
+#undef HM_LAUNCH
+}
+
+template <typename T, typename I>
+static void launch_t(const HalfTables *t, const HalfBonds *hb, const Basis *b, double shift,
+                     const HxPass &p, hipStream_t st) {
+    HalfArgs<I> g{};
+    g.rankL = t->d_rankL;
+    g.unrankL = t->d_unrankL;
+    g.off = (const I *)t->d_off;
+    g.nbr = (const I *)hb->nbr;
+    g.hgroups = t->d_hgroups;
+    g.items = t->d_items;
+    g.groups = hb->groups;
+    g.n_items = (uint32_t)t->n_items;
+    g.K = t->K;
+    g.A = b->A;
+    g.nLg = hb->nLg;
+    g.nHg = hb->nHg;
+    g.nSg = hb->nSg;
+    g.width = (hb->nHg + hb->nSg) * kGroup;
+    g.shift = shift;
+    for (int a = 0; a <= kHalfMaxK + 1; ++a) {
+        g.class_start[a] = t->class_start[a];
+        g.class_size[a] = t->class_size[a];
+    }
+    switch (t->R) {
+        case 1: launch_r<T, I, 1>(t, g, p, st); break;
+        case 2: launch_r<T, I, 2>(t, g, p, st); break;
+        case 4: launch_r<T, I, 4>(t, g, p, st); break;
+        default: launch_r<T, I, 8>(t, g, p, st); break;
+    }
+}
+
+// Builds the tables and the regrouped bonds (also ahead of a graph capture:
+// no allocation may happen while a stream is capturing).
+int half_prepare_tables(Basis *b, const Couplings *c) {
+    HalfTables *t = nullptr;
+    HM_TRY(half_prepare(b, &t));
+    const HalfBonds *hb = nullptr;
+    return half_bonds(b, c, t, &hb);
+}
+
+// Whether the block kernel can run these couplings (neighbour table budget).
+bool half_fits(const Basis *b, const Couplings *c) {
+    return half_supported(b) && neighbour_bytes(b, c, low_bits_of(b)) <= kMaxNeighbourBytes;
+}
+
+int launch_hx_half(const Basis *cb, const Couplings *c, int dtype, const HxPass &p,
+                   hipStream_t st) {
+    Basis *b = const_cast<Basis *>(cb);
+    HalfTables *t = nullptr;
+    HM_TRY(half_prepare(b, &t));
+    const HalfBonds *hb = nullptr;
+    HM_TRY(half_bonds(b, c, t, &hb));
+    if (dtype == HM_F64) {
+        if (b->idx32) launch_t<double, uint32_t>(t, hb, b, c->diag_shift, p, st);
+        else launch_t<double, uint64_t>(t, hb, b, c->diag_shift, p, st);
+    } else {
+        if (b->idx32) launch_t<float, uint32_t>(t, hb, b, c->diag_shift, p, st);
+        else launch_t<float, uint64_t>(t, hb, b, c->diag_shift, p, st);
+    }
+    HM_HIP(hipGetLastError());
+    return HM_OK;
 }
 
 }  // namespace hm

@@ -31,11 +31,17 @@ int launch_hx_half(const Basis *b, const Couplings *c, int dtype, const HxPass &
                    hipStream_t st);
 int hx_half_grid(const Basis *b);
 bool half_supported(const Basis *b);
+int half_prepare_tables(Basis *b, const Couplings *c);
+bool half_fits(const Basis *b, const Couplings *c);
 
-int choose_kernel(const Basis *b, int requested) {
+// 0 = automatic (the spin-1/2 block kernel when it applies to the basis and
+// its neighbour table fits the budget, else the generic digit kernel),
+// 1 = generic, 2 = block kernel (-1 if it does not apply).
+int choose_kernel(const Basis *b, const Couplings *c, int requested) {
     if (requested == 1) return 1;
-    if (requested == 2) return half_supported(b) ? 2 : -1;
-    return half_supported(b) ? 2 : 1;
+    const bool ok = c ? half_fits(b, c) : half_supported(b);
+    if (requested == 2) return ok ? 2 : -1;
+    return ok ? 2 : 1;
 }
 
 int hx_partial_count(const Basis *b, int kernel) {
@@ -73,12 +79,13 @@ static int vec_grid(int64_t n) {
     return (int)g;
 }
 
-static Layout layout(const Basis *b, int steps, int prec, int reorth, int kernel) {
+// Workspace layout; the partial-sum area holds kMaxGrid entries, enough for
+// any H x kernel, so the layout does not depend on the kernel choice.
+static Layout layout(const Basis *b, int steps, int prec, int reorth) {
     Layout L{};
     const size_t es = prec == HM_PREC_F64 ? 8 : 4;
     L.grid_vec = vec_grid(b->dim);
-    const int ghx = hx_partial_count(b, kernel);
-    L.nparts = std::max(L.grid_vec, ghx);
+    L.nparts = kMaxGrid;
     size_t partial_len = (size_t)L.nparts;
     if (reorth) partial_len = std::max(partial_len, (size_t)L.grid_vec * (size_t)steps);
     size_t off = 0;
@@ -453,13 +460,13 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
     return HM_OK;
 }
 
-static int check_opts(const Basis *b, const hm_lanczos_opts *o, int *kernel) {
+static int check_opts(const Basis *b, const hm_lanczos_opts *o) {
     if (!o) return fail(HM_EINVAL, "opts is null");
     if (o->precision != HM_PREC_F64 && o->precision != HM_PREC_F32_MIXED)
         return fail(HM_EINVAL, "unknown precision %d", o->precision);
     if (o->kernel < 0 || o->kernel > 2) return fail(HM_EINVAL, "unknown kernel %d", o->kernel);
-    *kernel = choose_kernel(b, o->kernel);
-    if (*kernel < 0) return fail(HM_EINVAL, "spin-1/2 block kernel not applicable to this basis");
+    if (choose_kernel(b, nullptr, o->kernel) < 0)
+        return fail(HM_EINVAL, "spin-1/2 block kernel not applicable to this basis");
     return HM_OK;
 }
 
@@ -470,10 +477,12 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     if (!h || !d_v0 || !d_work || !steps_done) return fail(HM_EINVAL, "null argument");
     if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
     Basis *b = &h->impl;
-    int kernel = 0;
-    HM_TRY(check_opts(b, o, &kernel));
+    HM_TRY(check_opts(b, o));
     const Couplings *c = nullptr;
     HM_TRY(get_couplings(b, J, &c));
+    const int kernel = choose_kernel(b, c, o->kernel);
+    if (kernel < 0) return fail(HM_ERANGE, "block kernel tables too large for these couplings");
+    if (kernel == 2) HM_TRY(half_prepare_tables(b, c));
     Run R{};
     R.b = b;
     R.c = c;
@@ -483,7 +492,7 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     R.kernel = kernel;
     R.use_graph = o->use_graph ? 1 : 0;
     R.tol = o->breakdown_tol > 0 ? o->breakdown_tol : 1e-12;
-    R.L = layout(b, steps, R.prec, R.reorth, kernel);
+    R.L = layout(b, steps, R.prec, R.reorth);
     if (work_bytes < R.L.total)
         return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, R.L.total);
     R.w = (unsigned char *)d_work;
@@ -636,9 +645,8 @@ int hm_lanczos_workspace(hm_basis h, int32_t steps, const hm_lanczos_opts *o, si
     hm::clear_error();
     if (!h || !bytes) return fail(HM_EINVAL, "null argument");
     if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
-    int kernel = 0;
-    HM_TRY(hm::check_opts(&h->impl, o, &kernel));
-    *bytes = hm::layout(&h->impl, steps, o->precision, o->full_reorth ? 1 : 0, kernel).total;
+    HM_TRY(hm::check_opts(&h->impl, o));
+    *bytes = hm::layout(&h->impl, steps, o->precision, o->full_reorth ? 1 : 0).total;
     return HM_OK;
 }
 
