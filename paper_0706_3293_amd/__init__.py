@@ -9,3 +9,4 @@ include/hm.h); this package is its thin Python binding:
   lanczos_batched  many instances and start vectors in one persistent launch
 """
 from .api import Basis, LanczosResult, count, last_timing, set_timing, tridiag_lowest  # noqa: F401
+from .autograd import GroundStateEnergy, ground_state, ground_state_energy  # noqa: F401,E402

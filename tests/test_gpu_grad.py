@@ -1,0 +1,126 @@
+"""GPU checks of the differentiable ground-state energy (N=20 all-to-all
+workload and smaller cases): gradient against the oracle's stored-basis
+gradient, central finite differences (h=1e-5, FP64), Euler's identity and
+the total-spin sum rule; the recompute pass must reproduce the forward
+coefficients bit for bit."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _setup(N=20, seed=0):
+    from paper_0706_3293_amd import Basis, inputs
+    J, bonds, vals = inputs.all_to_all_couplings(N, seed)
+    b = Basis(N, two_s=1, two_M=0)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+    return b, bonds, vals, v0
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_gradient_all_to_all20_matches_oracle(kernel):
+    from paper_0706_3293_amd import ground_state_energy
+    g = json.load(open(os.path.join(GOLDEN, "all_to_all20_oracle.json")))
+    b, bonds, vals, v0 = _setup()
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    E0 = ground_state_energy(Jv, b, bonds, v0, 300, kernel=kernel)
+    E0.backward()
+    grad = Jv.grad.numpy()
+    print(f"E0 {float(E0):.15f} oracle {g['E0']:.15f}; "
+          f"max|dgrad| {np.abs(grad - g['grad']).max():.2e}", flush=True)
+    assert abs(float(E0) - g["E0"]) <= 1e-10 * abs(g["E0"])
+    assert np.abs(grad - np.array(g["grad"])).max() < 1e-8
+    # Euler: H is linear in J, so sum_b J_b dE0/dJ_b = E0
+    assert abs(np.dot(vals, grad) - float(E0)) < 1e-9
+    # all pairs are bonds: sum_b <s_u.s_v> = (S(S+1) - N s(s+1)) / 2, integer S
+    S2 = -2 * grad.sum() + 20 * 0.75
+    S = (-1 + math.sqrt(max(1 + 4 * S2, 0))) / 2
+    assert abs(S - round(S)) < 1e-6
+
+
+def test_gradient_all_to_all20_finite_differences():
+    """Central differences of E0 for all 190 bonds, h = 1e-5, FP64."""
+    from paper_0706_3293_amd import ground_state_energy
+    from paper_0706_3293_amd.autograd import couplings_matrix
+    b, bonds, vals, v0 = _setup()
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    E0 = ground_state_energy(Jv, b, bonds, v0, 300)
+    E0.backward()
+    grad = Jv.grad.numpy()
+    h = 1e-5
+    fd = np.empty(len(bonds))
+    for k in range(len(bonds)):
+        e = []
+        for sgn in (1.0, -1.0):
+            vv = vals.copy()
+            vv[k] += sgn * h
+            e.append(b.lanczos(couplings_matrix(20, bonds, vv), v0, 300).E0)
+        fd[k] = (e[0] - e[1]) / (2 * h)
+    err = np.abs(grad - fd).max()
+    print(f"max |grad - FD| = {err:.2e}", flush=True)
+    assert err < 2e-6
+
+
+def test_recompute_pass_is_bitwise_identical():
+    from paper_0706_3293_amd import tridiag_lowest
+    from paper_0706_3293_amd.autograd import couplings_matrix
+    b, bonds, vals, v0 = _setup()
+    J = couplings_matrix(20, bonds, vals)
+    for prec in ("f64", "f32_mixed"):
+        res = b.lanczos(J, v0, 120, precision=prec)
+        _, c = tridiag_lowest(res.alpha, res.beta)
+        psi, a2, b2 = b.ritz(J, v0, res.steps_done, c, precision=prec)
+        assert np.array_equal(a2, res.alpha) and np.array_equal(b2, res.beta)
+        assert abs(float(torch.linalg.norm(psi)) - 1) < 1e-12
+
+
+def test_gradient_mixed_precision_error_is_small():
+    from paper_0706_3293_amd import ground_state_energy
+    g = json.load(open(os.path.join(GOLDEN, "all_to_all20_oracle.json")))
+    b, bonds, vals, v0 = _setup()
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    E0 = ground_state_energy(Jv, b, bonds, v0, 300, precision="f32_mixed")
+    E0.backward()
+    rel = abs(float(E0) - g["E0"]) / abs(g["E0"])
+    gerr = np.abs(Jv.grad.numpy() - np.array(g["grad"])).max()
+    print(f"mixed: rel dE0 {rel:.2e}, max |dgrad| {gerr:.2e}", flush=True)
+    assert rel < 1e-7
+    assert gerr < 1e-4
+
+
+def test_gradient_small_general_spin_vs_dense():
+    """s=1, N=6: gradient against the dense eigenvector of the Kronecker-built
+    Hamiltonian."""
+    from oracle import brute
+    from paper_0706_3293_amd import Basis, ground_state_energy
+    N, two_s, A = 6, 2, 6
+    rng = np.random.default_rng(3)
+    bonds = [(u, v) for u in range(N) for v in range(u + 1, N)]
+    vals = rng.normal(size=len(bonds))
+    b = Basis(N, two_s=two_s, two_M=0)
+    v0 = torch.tensor(rng.uniform(-1, 1, b.dim), device="cuda")
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    E0 = ground_state_energy(Jv, b, bonds, v0, 80)
+    E0.backward()
+    from paper_0706_3293_amd.autograd import couplings_matrix
+    Hd = brute.subspace_hamiltonian(N, two_s, A, couplings_matrix(N, bonds, vals))
+    w, z = np.linalg.eigh(Hd)
+    assert w[1] - w[0] > 1e-6
+    dense = np.array([-(z[:, 0] @ brute.subspace_bond_operator(N, two_s, A, u, v) @ z[:, 0])
+                      for u, v in bonds])
+    assert abs(float(E0) - w[0]) < 1e-10
+    assert np.abs(Jv.grad.numpy() - dense).max() < 1e-8
