@@ -165,7 +165,8 @@ int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y,
 typedef struct hm_lanczos_opts {
     int32_t precision;    /* HM_PREC_F64 or HM_PREC_F32_MIXED               */
     int32_t full_reorth;  /* 1: classical Gram-Schmidt twice vs all v_j     */
-    double breakdown_tol; /* relative; <= 0 selects 1e-12                   */
+    double breakdown_tol; /* relative; <= 0 selects 1e-12 (FP64) or 1e-6     *
+                           * (FP32-mixed: the FP32 rounding floor of beta) */
     int32_t use_graph;    /* 1: capture all steps in one hipGraph           */
     int32_t kernel;       /* 0: automatic choice of H x kernel; 1: generic
                              digit kernel; 2: spin-1/2 block kernel (if the

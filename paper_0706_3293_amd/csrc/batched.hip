@@ -1,18 +1,565 @@
-// Batched persistent Lanczos (placeholder until the persistent kernel lands).
+// Batched Lanczos: many independent problems (basis, couplings) with up to 16
+// start vectors each, all steps in one persistent cooperative launch.
+//
+// Vectors are stored in FP32 as [dim][NV] rows (NV = 1, 2, 4, 8 or 16), so the
+// multi-vector product H X decodes each basis state and encodes each target
+// once (Sec. 3.1, 3.2) and gathers the NV entries of a target row with
+// contiguous 16-byte loads.  Dots and norms are FP64.  Each (instance,
+// vector) pair runs its own recurrence (Paige's ordering, as hm_lanczos):
+//
+//   init  norms of the start vectors, r_0 = v0 / |v0|            (2 barriers)
+//   step  A:  w = sigma H r - cprev r_prev, alpha partials per item and vector
+//         A': alpha per pair, summed over the instance's items in fixed order
+//         B:  w -= alpha sigma r, |w|^2 partials
+//         B': beta, breakdown test, sigma and cprev of the next step
+// Work items are 256-row tiles of one instance; workgroups are persistent and
+// walk the items in a fixed order, so every sum has a fixed order.  The grid
+// barrier is a counter and a generation word with a bounded spin: a wave that
+// waits too long raises an abort flag and every wave leaves the kernel.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.h"
 #include "hm_internal.h"
+
+namespace hm {
+
+constexpr int kBatchBlock = 256;
+constexpr int kBatchMaxVec = 16;
+constexpr size_t kBatchPrefixLds = 24 * 1024;
+constexpr long long kSpinLimit = 1ll << 22;
+
+struct InstDesc {
+    int N, A, two_s, nb;
+    uint32_t dim;
+    uint32_t vec_off;          // first row of this instance in the stacked vectors
+    uint32_t item_first, item_count;
+    const uint32_t *prefix;    // 32-bit prefix table of the basis
+    const double *ladder;
+    const BondDev *bonds;
+    const double *v0;          // [dim][nvec] FP64 start vectors
+};
+
+struct Item {
+    uint32_t inst, row0;
+};
+
+struct GridBar {
+    unsigned count, gen;
+    int abort;
+    int pad;
+};
+
+struct BatchArgs {
+    const InstDesc *inst;
+    const Item *items;
+    int ninst, n_items, nvec, steps;
+    double tol;
+    GridBar *bar;
+    float *r[3];
+    double *partial;           // [n_items][NV]
+    double *alpha, *beta;      // [npairs][steps]
+    double *sigma, *cprev;     // [npairs][steps + 1]
+    double *scale, *norm0;     // [npairs]
+    int *stopped;              // [npairs]: steps done at breakdown, 0 while running
+    int max_prefix;            // entries of the largest prefix table
+};
+
+// Grid-wide barrier; returns false if the run was aborted (timeout).
+__device__ bool grid_barrier(GridBar *bar, unsigned nblocks, int *lds_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        int ok = __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        const unsigned g = __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_ACQ_REL,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (ok && __hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE,
+                                           __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                }
+                if ((spins & 1023) == 0 &&
+                    __hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    ok = 0;
+            }
+        }
+        __threadfence();
+        *lds_ok = ok;
+    }
+    __syncthreads();
+    return *lds_ok != 0;
+}
+
+template <int NV>
+__device__ __forceinline__ void load_row(const float *__restrict__ p, float (&v)[NV]) {
+    if constexpr (NV % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < NV / 4; ++q) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[q];
+            v[4 * q] = t.x;
+            v[4 * q + 1] = t.y;
+            v[4 * q + 2] = t.z;
+            v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = p[q];
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void store_row(float *__restrict__ p, const float (&v)[NV]) {
+    if constexpr (NV % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < NV / 4; ++q)
+            reinterpret_cast<float4 *>(p)[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2],
+                                                           v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) p[q] = v[q];
+    }
+}
+
+// Per-item FP64 partials of NV columns: each thread stages its NV values in
+// LDS, then thread q < NV sums column q over the workgroup in thread order.
+template <int NV>
+__device__ __forceinline__ void item_partials(const double (&v)[NV], double *stage,
+                                              double *out) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) stage[threadIdx.x * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int t = 0; t < (int)blockDim.x; ++t) s += stage[t * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+template <int NV, int B>
+__global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int ok_flag;
+    __shared__ double sc_sigma[NV], sc_c[NV], sc_a[NV];
+    uint32_t *P = reinterpret_cast<uint32_t *>(smem);
+    double *F = reinterpret_cast<double *>(smem + ((a.max_prefix * 4 + 15) / 16) * 16);
+    double *stage = F + 32;
+    const unsigned nblocks = gridDim.x;
+    const int npairs = a.ninst * NV;
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gthreads = gridDim.x * blockDim.x;
+
+    // ---- init: |v0| partials per item -----------------------------------
+    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item itm = a.items[it];
+        const InstDesc &d = a.inst[itm.inst];
+        const uint32_t i = itm.row0 + threadIdx.x;
+        double s[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s[q] = 0.0;
+        if (i < d.dim)
+            for (int q = 0; q < a.nvec; ++q) {
+                const double v = d.v0[(size_t)i * a.nvec + q];
+                s[q] = v * v;
+            }
+        item_partials<NV>(s, stage, a.partial + (size_t)it * NV);
+    }
+    if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+    for (int p = gtid; p < npairs; p += gthreads) {
+        const InstDesc &d = a.inst[p / NV];
+        const int q = p % NV;
+        double s = 0.0;
+        for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
+            s += a.partial[(size_t)it * NV + q];
+        const bool live = q < a.nvec && s > 0.0;
+        a.norm0[p] = sqrt(s);
+        a.scale[p] = 0.0;
+        a.stopped[p] = live ? 0 : -1;
+        a.sigma[(size_t)p * (a.steps + 1)] = live ? 1.0 : 0.0;
+        a.cprev[(size_t)p * (a.steps + 1)] = 0.0;
+    }
+    if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item itm = a.items[it];
+        const InstDesc &d = a.inst[itm.inst];
+        const uint32_t i = itm.row0 + threadIdx.x;
+        if (i < d.dim) {
+            float v[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const int p = itm.inst * NV + q;
+                v[q] = (q < a.nvec && a.stopped[p] == 0)
+                           ? (float)(d.v0[(size_t)i * a.nvec + q] / a.norm0[p]) : 0.0f;
+            }
+            store_row<NV>(a.r[0] + ((size_t)d.vec_off + i) * NV, v);
+        }
+    }
+    if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+
+    int loaded = -1;   // instance whose tables are in LDS
+    for (int k = 0; k < a.steps; ++k) {
+        const float *__restrict__ rk = a.r[k % 3];
+        const float *__restrict__ rp = a.r[(k + 2) % 3];
+        float *__restrict__ w = a.r[(k + 1) % 3];
+        // ---- A: w = sigma H r_k - cprev r_{k-1}; alpha partials ----------
+        for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+            const Item itm = a.items[it];
+            const InstDesc &d = a.inst[itm.inst];
+            if ((int)itm.inst != loaded) {
+                const int plen = d.N * (d.A + 1) * (d.two_s + 1);
+                for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = d.prefix[t];
+                for (int t = threadIdx.x; t < d.two_s + 2; t += blockDim.x) F[t] = d.ladder[t];
+                loaded = itm.inst;
+            }
+            if (threadIdx.x < NV) {
+                const int p = itm.inst * NV + threadIdx.x;
+                sc_sigma[threadIdx.x] = a.sigma[(size_t)p * (a.steps + 1) + k];
+                sc_c[threadIdx.x] = a.cprev[(size_t)p * (a.steps + 1) + k];
+            }
+            __syncthreads();
+            const Prefix<uint32_t> pv{P, d.A + 1, d.two_s + 1};
+            const uint32_t i = itm.row0 + threadIdx.x;
+            double dots[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) dots[q] = 0.0;
+            if (i < d.dim) {
+                const float *__restrict__ xr = rk + (size_t)d.vec_off * NV;
+                const uint64_t st = unrank_state<uint32_t, B>(i, pv, d.N, d.A, d.two_s);
+                float xi[NV], acc[NV];
+                load_row<NV>(xr + (size_t)i * NV, xi);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) acc[q] = 0.0f;
+                float diag = 0.0f;
+                for (int b = 0; b < d.nb; ++b) {
+                    const int u = d.bonds[b].u, v = d.bonds[b].v;
+                    const float mJ4 = (float)d.bonds[b].mJ4;
+                    const double mJ2 = d.bonds[b].mJ2;
+                    const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
+                    diag += mJ4 * (float)((d.two_s - 2 * au) * (d.two_s - 2 * av));
+                    if (au >= 1 && av < d.two_s) {
+                        const uint32_t j = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
+                        const float c = (float)(mJ2 * F[au] * F[av + 1]);
+                        float xj[NV];
+                        load_row<NV>(xr + (size_t)j * NV, xj);
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) acc[q] += c * xj[q];
+                    }
+                    if (av >= 1 && au < d.two_s) {
+                        const uint32_t j = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
+                        const float c = (float)(mJ2 * F[av] * F[au + 1]);
+                        float xj[NV];
+                        load_row<NV>(xr + (size_t)j * NV, xj);
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) acc[q] += c * xj[q];
+                    }
+                }
+                float prv[NV];
+                if (k > 0) load_row<NV>(rp + ((size_t)d.vec_off + i) * NV, prv);
+                float out[NV];
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    const double hv = (double)(diag * xi[q] + acc[q]);
+                    double wq = sc_sigma[q] * hv;
+                    if (k > 0) wq -= sc_c[q] * (double)prv[q];
+                    out[q] = (float)wq;
+                    dots[q] = (double)out[q] * (sc_sigma[q] * (double)xi[q]);
+                }
+                store_row<NV>(w + ((size_t)d.vec_off + i) * NV, out);
+            }
+            item_partials<NV>(dots, stage, a.partial + (size_t)it * NV);
+        }
+        if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+        // ---- A': alpha per pair --------------------------------------------
+        for (int p = gtid; p < npairs; p += gthreads) {
+            const InstDesc &d = a.inst[p / NV];
+            const int q = p % NV;
+            double s = 0.0;
+            for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
+                s += a.partial[(size_t)it * NV + q];
+            a.alpha[(size_t)p * a.steps + k] = s;
+        }
+        if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+        // ---- B: w -= alpha sigma r_k; |w|^2 partials -----------------------
+        for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+            const Item itm = a.items[it];
+            const InstDesc &d = a.inst[itm.inst];
+            if (threadIdx.x < NV) {
+                const int p = itm.inst * NV + threadIdx.x;
+                sc_a[threadIdx.x] = a.alpha[(size_t)p * a.steps + k] *
+                                    a.sigma[(size_t)p * (a.steps + 1) + k];
+            }
+            __syncthreads();
+            const uint32_t i = itm.row0 + threadIdx.x;
+            double ss[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) ss[q] = 0.0;
+            if (i < d.dim) {
+                const size_t row = ((size_t)d.vec_off + i) * NV;
+                float wv[NV], rv[NV];
+                load_row<NV>(w + row, wv);
+                load_row<NV>(rk + row, rv);
+#pragma unroll
+                for (int q = 0; q < NV; ++q) {
+                    wv[q] = (float)((double)wv[q] - sc_a[q] * (double)rv[q]);
+                    ss[q] = (double)wv[q] * (double)wv[q];
+                }
+                store_row<NV>(w + row, wv);
+            }
+            item_partials<NV>(ss, stage, a.partial + (size_t)it * NV);
+        }
+        if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+        // ---- B': beta, breakdown, next sigma / cprev -----------------------
+        for (int p = gtid; p < npairs; p += gthreads) {
+            const InstDesc &d = a.inst[p / NV];
+            const int q = p % NV;
+            double s = 0.0;
+            for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
+                s += a.partial[(size_t)it * NV + q];
+            const double b = sqrt(s);
+            const size_t o = (size_t)p * (a.steps + 1);
+            if (a.stopped[p] != 0) {
+                a.beta[(size_t)p * a.steps + k] = 0.0;
+                a.sigma[o + k + 1] = 0.0;
+                a.cprev[o + k + 1] = 0.0;
+                continue;
+            }
+            a.beta[(size_t)p * a.steps + k] = b;
+            const double sc = fmax(a.scale[p], fmax(fabs(a.alpha[(size_t)p * a.steps + k]), b));
+            a.scale[p] = sc;
+            if (!(b > a.tol * sc)) {
+                a.stopped[p] = k + 1;
+                a.sigma[o + k + 1] = 0.0;
+                a.cprev[o + k + 1] = 0.0;
+            } else {
+                a.sigma[o + k + 1] = 1.0 / b;
+                a.cprev[o + k + 1] = b * a.sigma[o + k];
+            }
+        }
+        if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+    size_t desc, items, bar, alpha, beta, sigma, cprev, scale, norm0, stopped, partial, r0, r1,
+        r2, total;
+    int n_items, NV;
+    uint64_t rows;
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int vec_width(int nvec) {
+    int NV = 1;
+    while (NV < nvec) NV <<= 1;
+    return NV;
+}
+
+static int batch_layout(int ninst, const hm_basis *bases, int nvec, int steps, BatchLayout *L) {
+    if (ninst < 1) return fail(HM_EINVAL, "ninst must be >= 1");
+    if (!bases) return fail(HM_EINVAL, "bases is null");
+    if (nvec < 1 || nvec > kBatchMaxVec) return fail(HM_EINVAL, "nvec must be 1..16");
+    if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
+    L->NV = vec_width(nvec);
+    L->n_items = 0;
+    L->rows = 0;
+    for (int k = 0; k < ninst; ++k) {
+        if (!bases[k]) return fail(HM_EINVAL, "basis %d is null", k);
+        const Basis &b = bases[k]->impl;
+        if (b.two_s != bases[0]->impl.two_s)
+            return fail(HM_EINVAL, "all instances must share the spin (basis %d differs)", k);
+        if (!b.idx32) return fail(HM_ERANGE, "basis %d: dimension too large for the batch", k);
+        if (b.prefix_len() * 4 > kBatchPrefixLds)
+            return fail(HM_ERANGE, "basis %d: prefix table exceeds the batch LDS budget", k);
+        L->n_items += (int)((b.dim + kBatchBlock - 1) / kBatchBlock);
+        L->rows += (uint64_t)b.dim;
+    }
+    if (L->rows >= ((uint64_t)1 << 32)) return fail(HM_ERANGE, "too many rows in the batch");
+    const size_t npairs = (size_t)ninst * L->NV;
+    size_t off = 0;
+    L->desc = off; off = al256(off + sizeof(InstDesc) * ninst);
+    L->items = off; off = al256(off + sizeof(Item) * L->n_items);
+    L->bar = off; off = al256(off + sizeof(GridBar));
+    L->alpha = off; off = al256(off + sizeof(double) * npairs * steps);
+    L->beta = off; off = al256(off + sizeof(double) * npairs * steps);
+    L->sigma = off; off = al256(off + sizeof(double) * npairs * (steps + 1));
+    L->cprev = off; off = al256(off + sizeof(double) * npairs * (steps + 1));
+    L->scale = off; off = al256(off + sizeof(double) * npairs);
+    L->norm0 = off; off = al256(off + sizeof(double) * npairs);
+    L->stopped = off; off = al256(off + sizeof(int) * npairs);
+    L->partial = off; off = al256(off + sizeof(double) * (size_t)L->n_items * L->NV);
+    const size_t vb = sizeof(float) * (size_t)L->rows * L->NV;
+    L->r0 = off; off = al256(off + vb);
+    L->r1 = off; off = al256(off + vb);
+    L->r2 = off; off = al256(off + vb);
+    L->total = off;
+    return HM_OK;
+}
+
+template <int NV, int B>
+static int launch_batched(BatchArgs &args, size_t lds, hipStream_t st, int *grid_out) {
+    auto kern = batched_lanczos_kernel<NV, B>;
+    int dev = 0, per_cu = 0;
+    HM_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HM_HIP(hipGetDeviceProperties(&prop, dev));
+    HM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchBlock, lds));
+    if (per_cu < 1) return fail(HM_ERANGE, "batched kernel does not fit on a compute unit");
+    int grid = std::min(per_cu, 4) * prop.multiProcessorCount;
+    grid = std::min(grid, std::max(args.n_items, 1));
+    *grid_out = grid;
+    void *params[] = {&args};
+    HM_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(kBatchBlock), params,
+                                      (unsigned)lds, st));
+    return HM_OK;
+}
+
+template <int NV>
+static int dispatch_bits(int bits, BatchArgs &args, size_t lds, hipStream_t st, int *grid) {
+    switch (bits) {
+        case 1: return launch_batched<NV, 1>(args, lds, st, grid);
+        case 2: return launch_batched<NV, 2>(args, lds, st, grid);
+        case 3: return launch_batched<NV, 3>(args, lds, st, grid);
+        case 4: return launch_batched<NV, 4>(args, lds, st, grid);
+        default: return fail(HM_ERANGE, "batched kernel supports up to 4 bits per digit");
+    }
+}
+
+__global__ void zero_bar(GridBar *bar) {
+    bar->count = 0;
+    bar->gen = 0;
+    bar->abort = 0;
+    bar->pad = 0;
+}
+
+}  // namespace hm
 
 using hm::fail;
 
 extern "C" {
 
-int hm_lanczos_batched_workspace(int32_t, const hm_basis *, int32_t, int32_t, size_t *) {
-    return fail(HM_EINVAL, "batched Lanczos not available in this build");
+int hm_lanczos_batched_workspace(int32_t ninst, const hm_basis *bases, int32_t nvec,
+                                 int32_t steps, size_t *bytes) {
+    hm::clear_error();
+    if (!bytes) return fail(HM_EINVAL, "bytes is null");
+    hm::BatchLayout L;
+    HM_TRY(hm::batch_layout(ninst, bases, nvec, steps, &L));
+    *bytes = L.total;
+    return HM_OK;
 }
 
-int hm_lanczos_batched(int32_t, const hm_basis *, const double *const *, const double *const *,
-                       int32_t, int32_t, double, void *, size_t, double *, double *, double *,
-                       int32_t *, void *) {
-    return fail(HM_EINVAL, "batched Lanczos not available in this build");
+int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const *J,
+                       const double *const *d_v0, int32_t nvec, int32_t steps,
+                       double breakdown_tol, void *d_work, size_t work_bytes, double *alpha,
+                       double *beta, double *E0, int32_t *steps_done, void *stream) {
+    hm::clear_error();
+    if (!J || !d_v0 || !d_work || !alpha || !beta || !E0 || !steps_done)
+        return fail(HM_EINVAL, "null argument");
+    hm::BatchLayout L;
+    HM_TRY(hm::batch_layout(ninst, bases, nvec, steps, &L));
+    if (work_bytes < L.total)
+        return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, L.total);
+    unsigned char *w = (unsigned char *)d_work;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<hm::InstDesc> desc(ninst);
+    std::vector<hm::Item> items;
+    uint32_t vec_off = 0;
+    int max_prefix = 0;
+    for (int k = 0; k < ninst; ++k) {
+        hm::Basis *b = &bases[k]->impl;
+        if (!d_v0[k]) return fail(HM_EINVAL, "start vectors of instance %d are null", k);
+        const hm::Couplings *c = nullptr;
+        HM_TRY(hm::get_couplings(b, J[k], &c));   // validates J and prepares the device
+        hm::InstDesc &d = desc[k];
+        d.N = b->N;
+        d.A = b->A;
+        d.two_s = b->two_s;
+        d.nb = c->nb;
+        d.dim = (uint32_t)b->dim;
+        d.vec_off = vec_off;
+        d.item_first = (uint32_t)items.size();
+        for (uint32_t r0 = 0; r0 < d.dim; r0 += hm::kBatchBlock) items.push_back({(uint32_t)k, r0});
+        d.item_count = (uint32_t)items.size() - d.item_first;
+        d.prefix = (const uint32_t *)b->d_prefix;
+        d.ladder = b->d_ladder;
+        d.bonds = c->dev;
+        d.v0 = d_v0[k];
+        vec_off += d.dim;
+        max_prefix = std::max(max_prefix, (int)b->prefix_len());
+    }
+    HM_HIP(hipMemcpyAsync(w + L.desc, desc.data(), sizeof(hm::InstDesc) * ninst,
+                          hipMemcpyHostToDevice, st));
+    HM_HIP(hipMemcpyAsync(w + L.items, items.data(), sizeof(hm::Item) * items.size(),
+                          hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(hm::zero_bar, dim3(1), dim3(1), 0, st, (hm::GridBar *)(w + L.bar));
+    HM_HIP(hipGetLastError());
+    hm::BatchArgs a{};
+    a.inst = (const hm::InstDesc *)(w + L.desc);
+    a.items = (const hm::Item *)(w + L.items);
+    a.ninst = ninst;
+    a.n_items = L.n_items;
+    a.nvec = nvec;
+    a.steps = steps;
+    a.tol = breakdown_tol > 0 ? breakdown_tol : 1e-6;   // FP32 vectors: FP32 noise floor
+    a.bar = (hm::GridBar *)(w + L.bar);
+    a.r[0] = (float *)(w + L.r0);
+    a.r[1] = (float *)(w + L.r1);
+    a.r[2] = (float *)(w + L.r2);
+    a.partial = (double *)(w + L.partial);
+    a.alpha = (double *)(w + L.alpha);
+    a.beta = (double *)(w + L.beta);
+    a.sigma = (double *)(w + L.sigma);
+    a.cprev = (double *)(w + L.cprev);
+    a.scale = (double *)(w + L.scale);
+    a.norm0 = (double *)(w + L.norm0);
+    a.stopped = (int *)(w + L.stopped);
+    a.max_prefix = max_prefix;
+    const size_t lds = ((size_t)(max_prefix * 4 + 15) / 16) * 16 + 32 * sizeof(double) +
+                       (size_t)hm::kBatchBlock * L.NV * sizeof(double);
+    const int bits = bases[0]->impl.bits;
+    int grid = 0, rc;
+    switch (L.NV) {
+        case 1: rc = hm::dispatch_bits<1>(bits, a, lds, st, &grid); break;
+        case 2: rc = hm::dispatch_bits<2>(bits, a, lds, st, &grid); break;
+        case 4: rc = hm::dispatch_bits<4>(bits, a, lds, st, &grid); break;
+        case 8: rc = hm::dispatch_bits<8>(bits, a, lds, st, &grid); break;
+        default: rc = hm::dispatch_bits<16>(bits, a, lds, st, &grid); break;
+    }
+    if (rc != HM_OK) return rc;
+    HM_HIP(hipStreamSynchronize(st));
+    hm::GridBar bar;
+    HM_HIP(hipMemcpy(&bar, w + L.bar, sizeof bar, hipMemcpyDeviceToHost));
+    if (bar.abort) return fail(HM_EDEVICE, "batched kernel: grid barrier timed out");
+    const size_t npairs = (size_t)ninst * L.NV;
+    std::vector<double> al(npairs * steps), be(npairs * steps);
+    std::vector<int> stop(npairs);
+    HM_HIP(hipMemcpy(al.data(), w + L.alpha, sizeof(double) * al.size(), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(be.data(), w + L.beta, sizeof(double) * be.size(), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(stop.data(), w + L.stopped, sizeof(int) * npairs, hipMemcpyDeviceToHost));
+    for (int k = 0; k < ninst; ++k)
+        for (int q = 0; q < nvec; ++q) {
+            const size_t p = (size_t)k * L.NV + q, o = ((size_t)k * nvec + q) * steps;
+            if (stop[p] < 0) return fail(HM_EINVAL, "start vector %d of instance %d is zero", q, k);
+            const int done = stop[p] > 0 ? stop[p] : steps;
+            for (int s = 0; s < steps; ++s) {
+                alpha[o + s] = s < done ? al[p * steps + s] : 0.0;
+                beta[o + s] = s < done ? be[p * steps + s] : 0.0;
+            }
+            steps_done[k * nvec + q] = done;
+            HM_TRY(hm_tridiag_lowest(done, alpha + o, beta + o, &E0[k * nvec + q], nullptr));
+        }
+    return HM_OK;
 }
 
 }  // extern "C"

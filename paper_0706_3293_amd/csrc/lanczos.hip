@@ -491,7 +491,8 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     R.reorth = o->full_reorth ? 1 : 0;
     R.kernel = kernel;
     R.use_graph = o->use_graph ? 1 : 0;
-    R.tol = o->breakdown_tol > 0 ? o->breakdown_tol : 1e-12;
+    R.tol = o->breakdown_tol > 0 ? o->breakdown_tol
+                                 : (R.prec == HM_PREC_F64 ? 1e-12 : 1e-6);
     R.L = layout(b, steps, R.prec, R.reorth);
     if (work_bytes < R.L.total)
         return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, R.L.total);
