@@ -7,13 +7,16 @@ flips, encode, gather), the alpha/beta reductions and the vector update.
 K steps are timed for the FP32-mixed path (vectors and matrix elements in
 FP32, dots/norms in FP64) and, separately, for the FP64 path; E0 of both is
 compared with the exact Majumdar-Ghosh value -3N/8 of this workload.
+--workload j1j2_ring32 runs the N=32, J2=-0.25 ring (dim 601,080,390).
 
-Prints one JSON line (rank 0, one GPU).  `value` is the whole-job
-throughput of the FP32-mixed path in rows/s (dim x K / time, inputs already
-resident in HBM); the FP64 throughput, the mixed/FP64 step ratio and the H x
-kernel measurements travel in extra fields.
+Prints one JSON line (one GPU).  `value` is the whole-job throughput of the
+FP32-mixed path in rows/s (dim x K / time, inputs already resident in HBM);
+the FP64 throughput, the mixed/FP64 step ratio, the H x kernel measurements,
+the roofline of the dominant kernel and the oracle's CPU rate travel in extra
+fields.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H·x rows/s + HBM GB/s; Lanczos steps/s, FP32-mixed vs FP64 at |ΔE0|<1e-7"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_0706_3293_amd", "csrc", "hx_half.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "hx_half_traffic.json")
 
 
 def parse():
@@ -33,27 +38,51 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="j1j2_ring28",
-                    choices=["j1j2_ring28", "j1j2_ring32"])
+    ap.add_argument("--workload", default="j1j2_ring28", choices=["j1j2_ring28", "j1j2_ring32"])
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 generic, 2 spin-1/2 block")
+    ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 23)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 24)
     ap.add_argument("--hx-repeats", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a 1 GiB device copy (profiling reference)")
     return ap.parse_args()
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per launch from the committed counter summary, or None if
+    the kernel source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha1") != kernel_hash():
+        return None
+    e = t.get("entries", {}).get(f"{workload}/{prec}")
+    return None if e is None else e.get("bytes_per_launch")
 
 
 def cpu_baseline(N, J, x, rows):
     """The oracle's row-gather H x on a random sample of rows (host cores)."""
     import oracle
     sub = oracle.Subspace(N, 1, N // 2)
-    rng = np.random.default_rng(1)
-    sample = np.sort(rng.integers(0, sub.dim, rows))
+    sample = np.sort(np.random.default_rng(1).integers(0, sub.dim, rows))
     t0 = time.perf_counter()
     sub.apply_rows(J, x, sample)
     dt = time.perf_counter() - t0
     return dict(value=rows / dt, unit="rows/s", cores=oracle.max_threads(), kind="oracle",
-                sample=f"oracle FP64 H x on {rows} random rows of the same workload "
-                       f"({dt:.1f} s)")
+                sample=f"oracle FP64 H x of {rows} random rows of the same workload "
+                       f"({dt:.1f} s on the host)")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -64,22 +93,40 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_0706_3293_amd import Basis, api, inputs
+    from paper_0706_3293_amd import Basis, api, autotune, inputs
 
     torch.cuda.set_device(0)
     w = inputs.WORKLOADS[args.workload]
     N = w["N"]
     J = inputs.workload_couplings(args.workload)
-    b = Basis(N, two_s=1, two_M=0)
-    D = b.dim
-    exact = {"j1j2_ring28": -3 * N / 8}.get(args.workload)
-    print(f"[bench] workload {args.workload} dim {D}", file=sys.stderr, flush=True)
+    exact = -3 * N / 8 if args.workload == "j1j2_ring28" else None
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies done")
+        del a, bb
+
+    bases, schedules = {}, {}
+    for prec, dt in (("f32_mixed", torch.float32), ("f64", torch.float64)):
+        if args.no_tune or args.kernel == 1:
+            bases[prec] = Basis(N, two_s=1, two_M=0)
+            schedules[prec] = None
+        else:
+            t0 = time.perf_counter()
+            bases[prec], schedules[prec] = autotune.tuned_basis(N, J, dtype=dt)
+            log(f"autotune {prec}: schedule (K, block, rows/lane) = {schedules[prec]} "
+                f"in {time.perf_counter() - t0:.1f} s")
+    D = bases["f64"].dim
+    log(f"workload {args.workload} dim {D}")
     v0_host = inputs.start_vector(D, w["seed"])
     v0 = torch.tensor(v0_host, device="cuda")
 
     results = {}
     for prec in ("f32_mixed", "f64"):
-        # warmup: a short run builds tables, uploads couplings, fills caches
+        b = bases[prec]
         b.lanczos(J, v0, max(args.warmup, 1), precision=prec, kernel=args.kernel)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -88,32 +135,34 @@ def main():
         dt = time.perf_counter() - t0
         results[prec] = dict(ms_per_step=1e3 * dt / args.steps, E0=res.E0,
                              steps_done=res.steps_done)
-        print(f"[bench] {prec}: {1e3 * dt / args.steps:.3f} ms/step E0={res.E0:.12f}",
-              file=sys.stderr, flush=True)
+        log(f"{prec}: {1e3 * dt / args.steps:.3f} ms/step E0={res.E0:.12f}")
 
-    # H x kernel time inside the Lanczos step, by HIP events on the call's stream
+    # H x pass inside the Lanczos step, timed by HIP events on the call's stream
     hx = {}
     for prec, es in (("f32_mixed", 4), ("f64", 8)):
         api.set_timing(True)
-        b.lanczos(J, v0, args.hx_repeats, precision=prec, kernel=args.kernel, use_graph=False)
+        bases[prec].lanczos(J, v0, args.hx_repeats, precision=prec, kernel=args.kernel,
+                            use_graph=False)
         api.set_timing(False)
         t = api.last_timing()
         avg_ms = t["hx_ms"] / max(t["hx_launches"], 1)
-        alg_bytes = 3 * es * D          # read x and previous vector, write w
-        hx[prec] = dict(avg_ms=avg_ms, alg_bytes=alg_bytes,
-                        gbs=alg_bytes / (avg_ms * 1e-3) / 1e9,
-                        rows_per_s=D / (avg_ms * 1e-3))
-        print(f"[bench] H x pass ({prec}): {avg_ms:.3f} ms, {hx[prec]['gbs']:.0f} GB/s "
-              "algorithmic", file=sys.stderr, flush=True)
+        alg_bytes = 3 * es * D          # read x and the previous vector, write w
+        traffic = measured_traffic(args.workload, prec)
+        hx[prec] = dict(avg_ms=avg_ms, launches=t["hx_launches"], alg_bytes=alg_bytes,
+                        alg_gbs=alg_bytes / (avg_ms * 1e-3) / 1e9,
+                        rows_per_s=D / (avg_ms * 1e-3), traffic_bytes=traffic,
+                        traffic_gbs=(traffic / (avg_ms * 1e-3) / 1e9) if traffic else None)
+        log(f"H x pass ({prec}): {avg_ms:.3f} ms, {hx[prec]['alg_gbs']:.0f} GB/s algorithmic")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, J, v0_host, args.cpu_rows)
-        print(f"[bench] cpu baseline {cpu['value']:.3g} rows/s on {cpu['cores']} threads",
-              file=sys.stderr, flush=True)
+        log(f"cpu baseline {cpu['value']:.3g} rows/s on {cpu['cores']} threads")
 
     mixed, f64 = results["f32_mixed"], results["f64"]
-    dE = {p: (abs(r["E0"] - exact) if exact is not None else None) for p, r in results.items()}
+    ref = exact if exact is not None else f64["E0"]
+    dE = {p: abs(r["E0"] - ref) for p, r in results.items()}
+    h32 = hx["f32_mixed"]
     line = {
         "metric": METRIC,
         "value": D / (mixed["ms_per_step"] * 1e-3),
@@ -127,20 +176,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: s=1/2 J1-J2 ring N={N}, M=0, dim {D}, "
-                               f"{args.steps} Lanczos steps, FP32-mixed",
-                   "dim": D, "parallelism": "single GPU"},
+        "config": {"workload": f"{args.workload}: s=1/2 J1-J2 ring N={N} M=0 (dim {D}), "
+                               f"{args.steps} Lanczos steps, FP32-mixed (FP64 dots)",
+                   "dim": D, "steps": args.steps, "parallelism": "single GPU",
+                   "schedule": {p: s for p, s in schedules.items()}},
         "lanczos_steps_per_s": {"f32_mixed": 1e3 / mixed["ms_per_step"],
                                 "f64": 1e3 / f64["ms_per_step"]},
         "mixed_over_f64_step_speedup": f64["ms_per_step"] / mixed["ms_per_step"],
         "f64_rows_per_s": D / (f64["ms_per_step"] * 1e-3),
         "E0": {"f32_mixed": mixed["E0"], "f64": f64["E0"], "exact": exact},
         "abs_dE0": dE,
-        "rel_dE0": {p: (v / abs(exact) if v is not None else None) for p, v in dE.items()},
+        "rel_dE0": {p: v / abs(ref) for p, v in dE.items()},
+        "dE0_reference": "exact -3N/8" if exact is not None else "FP64 path",
         "hx_pass": hx,
-        "roofline": {"bound": "hbm", "achieved": hx["f32_mixed"]["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": hx["f32_mixed"]["gbs"] / HBM_PEAK_GBS,
-                     "traffic": None},
+        "roofline": {"bound": "hbm", "achieved": h32["alg_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": h32["alg_gbs"] / HBM_PEAK_GBS,
+                     "traffic": h32["traffic_bytes"],
+                     "kernel": "hx_half_kernel<float, uint32, R, DOT=true>",
+                     "alg_bytes_per_launch": h32["alg_bytes"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -1,0 +1,99 @@
+"""Autotuner for the spin-1/2 block kernel's schedule.
+
+For a given problem (N, M, couplings, element type) every candidate schedule
+(low bits K, workgroup size, rows per lane) is built on a fresh basis handle
+and timed with HIP events over a few H x applications on the current stream;
+the fastest is returned and remembered in a JSON cache keyed by the problem.
+A chosen schedule is fixed for the lifetime of its basis handle, so the two
+Lanczos passes of the gradient (which must agree bit for bit) always run the
+same kernel configuration.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import torch
+
+from .api import Basis
+
+DEFAULT_CACHE = os.environ.get(
+    "HM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hm_autotune.json"))
+
+
+def candidates(N):
+    """Schedules worth trying for N sites (K, block threads, rows per lane)."""
+    out = []
+    for K in sorted({max(1, min(N, k)) for k in (10, 11, 12, 13, 14)}):
+        if N - K > 24:
+            continue
+        for R in (1, 2, 4, 8):
+            out.append((K, 256, R))
+    out.append((min(N, 12), 128, 4))
+    return out
+
+
+def _key(N, two_M, J, dtype):
+    h = hashlib.sha1(np.ascontiguousarray(np.asarray(J, dtype=np.float64)).tobytes()).hexdigest()
+    return f"N={N},2M={two_M},dtype={dtype},J={h[:16]}"
+
+
+def time_apply(b, J, x, y, reps):
+    """Average ms of one H x application (block kernel) by HIP events."""
+    b.apply(J, x, out=y, kernel=2)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        b.apply(J, x, out=y, kernel=2)
+    stop.record()
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbose=False):
+    """Best (K, block, R) for H x with these couplings; results are cached."""
+    key = _key(N, two_M, J, str(dtype))
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        return tuple(table[key]["schedule"])
+    probe = Basis(N, two_s=1, two_M=two_M)
+    x = torch.rand(probe.dim, dtype=dtype, device="cuda")
+    y = torch.empty_like(x)
+    del probe
+    best, best_ms, trials = None, float("inf"), []
+    for sched in candidates(N):
+        b = Basis(N, two_s=1, two_M=two_M)
+        b.set_schedule(*sched)
+        ms = time_apply(b, J, x, y, reps)
+        trials.append((sched, ms))
+        if verbose:
+            print(f"[autotune] K={sched[0]} block={sched[1]} R={sched[2]}: {ms:.3f} ms",
+                  flush=True)
+        if ms < best_ms:
+            best, best_ms = sched, ms
+        del b
+    if cache:
+        table[key] = {"schedule": list(best), "ms": best_ms,
+                      "trials": [[list(s), m] for s, m in trials]}
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        except OSError:
+            pass
+    return best
+
+
+def tuned_basis(N, J, two_M=0, dtype=torch.float32, **kw):
+    """A spin-1/2 basis whose block kernel runs the tuned schedule."""
+    sched = tune(N, J, two_M=two_M, dtype=dtype, **kw)
+    b = Basis(N, two_s=1, two_M=two_M)
+    b.set_schedule(*sched)
+    return b, sched
