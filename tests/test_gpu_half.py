@@ -142,3 +142,18 @@ def test_schedule_rejected_after_first_use():
         _basis(12, 6).set_schedule(8, 96)
     with pytest.raises(_lib.HMError):
         _basis(12, 6).set_schedule(8, 64, 3)
+
+
+def test_autotuner_picks_a_valid_schedule(tmp_path):
+    import oracle
+    from paper_0706_3293_amd import autotune, inputs
+    N = 18
+    J = inputs.ring_couplings(N, -1.0, -0.3)
+    cache = str(tmp_path / "tune.json")
+    b, sched = autotune.tuned_basis(N, J, reps=2, cache=cache)
+    assert sched in [tuple(c) for c in autotune.candidates(N)]
+    assert autotune.tune(N, J, reps=2, cache=cache) == sched      # cached
+    sub = oracle.Subspace(N, 1, N // 2)
+    x = np.random.default_rng(0).uniform(-1, 1, b.dim)
+    y = b.apply(J, torch.tensor(x, device="cuda"), kernel=2).cpu().numpy()
+    assert np.abs(y - sub.apply(J, x)).max() < 1e-12
