@@ -104,6 +104,12 @@ struct HalfArgs {
     int class_size[kHalfMaxK + 2];
 };
 
+// Element at a byte offset from a wave-uniform base pointer.
+template <typename T>
+__device__ __forceinline__ T load_at(const T *__restrict__ base, uint32_t byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 template <typename T> __device__ __forceinline__ T coef(const BondGroup &g, int q);
 template <> __device__ __forceinline__ float coef<float>(const BondGroup &g, int q) {
     return g.c32[q];
@@ -176,11 +182,14 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
         I off[R];
         const I *__restrict__ nb[R];
         T xi[R], acc[R];
+        // offsets inside a block are byte offsets from a wave-uniform block
+        // base, so loads take the scalar-base + 32-bit-offset address form
+        const uint32_t r_bytes = (uint32_t)r * (uint32_t)sizeof(T);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             off[m] = g.off[hs[m]];
             nb[m] = g.nbr + (size_t)hs[m] * g.width;
-            xi[m] = x[off[m] + (I)r];
+            xi[m] = load_at(x + off[m], r_bytes);
             acc[m] = 0;
         }
         // bonds inside the low word: the test and rankL(L ^ m) once per lane
@@ -193,19 +202,20 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             for (int q = 0; q < kGroup; ++q) idx[q] = rankL[L ^ mk[q]];
 #pragma unroll
             for (int q = 0; q < kGroup; ++q)
-                idx[q] = __popc(L & mk[q]) == 1 ? idx[q] : (uint32_t)r;
+                idx[q] = __popc(L & mk[q]) == 1 ? idx[q] * (uint32_t)sizeof(T) : r_bytes;
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const T *__restrict__ xb = x + off[m];
                 T xj[kGroup];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) xj[q] = xb[idx[q]];
+                for (int q = 0; q < kGroup; ++q) xj[q] = load_at(xb, idx[q]);
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
             }
         }
         // bonds inside the high word: tabulated target block (own block if
-        // the bond cannot flip), same low word
+        // the bond cannot flip), same low word; the test is wave-uniform, so a
+        // bond that cannot flip skips its load with a scalar branch
         for (int k = 0; k < g.nHg; ++k) {
             const BondGroup &G = gh[k];
 #pragma unroll
@@ -213,8 +223,8 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
                 T xj[kGroup];
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
-                    const T *__restrict__ xo = x + nb[m][k * kGroup + q];
-                    xj[q] = xo[(uint32_t)r];
+                    const I o = nb[m][k * kGroup + q];
+                    xj[q] = o != off[m] ? load_at(x + o, r_bytes) : xi[m];
                 }
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
