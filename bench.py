@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--hx-repeats", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a 1 GiB device copy (profiling reference)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the other workloads")
     return ap.parse_args()
 
 
@@ -83,6 +85,51 @@ def cpu_baseline(N, J, x, rows):
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def extras():
+    """Timings of the other measured workloads (one GPU, inputs resident)."""
+    import torch
+
+    from paper_0706_3293_amd import (Basis, BatchedProblem, ground_state_energy, inputs)
+    out = {}
+    # N=12 ring, 120 steps with full reorthogonalization, FP64
+    b = Basis(12, two_s=1, two_M=0)
+    J = inputs.ring_couplings(12, -1.0)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+    b.lanczos(J, v0, 120, full_reorth=True)
+    t0 = time.perf_counter()
+    res = b.lanczos(J, v0, 120, full_reorth=True)
+    out["ring12"] = dict(ms=1e3 * (time.perf_counter() - t0), steps=120, E0=res.E0)
+    # N=20 all-to-all: E0(J) forward (300 steps FP64) and gradient of 190 bonds
+    b = Basis(20, two_s=1, two_M=0)
+    J, bonds, vals = inputs.all_to_all_couplings(20, 0)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    ground_state_energy(Jv, b, bonds, v0, 300).backward()          # warm
+    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    t0 = time.perf_counter()
+    E0 = ground_state_energy(Jv, b, bonds, v0, 300)
+    t1 = time.perf_counter()
+    E0.backward()
+    t2 = time.perf_counter()
+    out["all_to_all20"] = dict(forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1),
+                               steps=300, bonds=len(bonds), E0=float(E0),
+                               euler_residual=abs(float(np.dot(vals, Jv.grad.numpy())) - float(E0)))
+    # 64 spin-1 chains x 16 start vectors x 80 steps, one persistent launch
+    inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)
+    bases = [Basis(d["N"], two_s=2, two_M=0) for d in inst]
+    prob = BatchedProblem(bases, [d["J"] for d in inst], [d["V0"] for d in inst], 80)
+    prob.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = prob.run()
+    dt = time.perf_counter() - t0
+    out["spin1_chains_batched"] = dict(
+        ms=1e3 * dt, instances=64, vectors=16, steps=80, rows=prob.rows,
+        row_vector_steps_per_s=prob.rows * 16 * 80 / dt,
+        E0_spread_max=float(np.max(np.ptp(r.E0, axis=1))))
+    return out
 
 
 def main():
@@ -154,6 +201,11 @@ def main():
                         traffic_gbs=(traffic / (avg_ms * 1e-3) / 1e9) if traffic else None)
         log(f"H x pass ({prec}): {avg_ms:.3f} ms, {hx[prec]['alg_gbs']:.0f} GB/s algorithmic")
 
+    other = None
+    if not args.no_extras:
+        other = extras()
+        log(f"other workloads: {json.dumps(other)}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, J, v0_host, args.cpu_rows)
@@ -195,6 +247,7 @@ def main():
                      "kernel": "hx_half_kernel<float, uint32, R, DOT=true>",
                      "alg_bytes_per_launch": h32["alg_bytes"]},
         "cpu_baseline": cpu,
+        "other_workloads": other,
     }
     print(json.dumps(line), flush=True)
 

@@ -10,4 +10,4 @@ include/hm.h); this package is its thin Python binding:
 """
 from .api import Basis, LanczosResult, count, last_timing, set_timing, tridiag_lowest  # noqa: F401
 from .autograd import GroundStateEnergy, ground_state, ground_state_energy  # noqa: F401,E402
-from .batched import BatchedResult, lanczos_batched  # noqa: F401,E402
+from .batched import BatchedProblem, BatchedResult, lanczos_batched  # noqa: F401,E402

@@ -9,7 +9,8 @@
 //
 //   init  norms of the start vectors, r_0 = v0 / |v0|            (2 barriers)
 //   step  A:  w = sigma H r - cprev r_prev, alpha partials per item and vector
-//         A': alpha per pair, summed over the instance's items in fixed order
+//         A': alpha per pair, one wave per pair summing the instance's item
+//             partials in a fixed order
 //         B:  w -= alpha sigma r, |w|^2 partials
 //         B': beta, breakdown test, sigma and cprev of the next step
 // Work items are 256-row tiles of one instance; workgroups are persistent and
@@ -129,20 +130,39 @@ __device__ __forceinline__ void store_row(float *__restrict__ p, const float (&v
     }
 }
 
-// Per-item FP64 partials of NV columns: each thread stages its NV values in
-// LDS, then thread q < NV sums column q over the workgroup in thread order.
+// Per-item FP64 partials of NV columns: a fixed butterfly per column inside
+// each wave, then thread q < NV adds the wave sums of column q in wave order.
 template <int NV>
-__device__ __forceinline__ void item_partials(const double (&v)[NV], double *stage,
-                                              double *out) {
+__device__ __forceinline__ void item_partials(double (&v)[NV], double *stage, double *out) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) stage[threadIdx.x * NV + q] = v[q];
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) stage[wid * NV + q] = v[q];
+    }
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0.0;
-        for (int t = 0; t < (int)blockDim.x; ++t) s += stage[t * NV + threadIdx.x];
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += stage[w * NV + threadIdx.x];
         out[threadIdx.x] = s;
     }
     __syncthreads();
+}
+
+// Sum of column q of the item partials [first, first + count): lane l adds
+// items l, l + 64, ... in order, then a fixed butterfly over the lanes.  Every
+// lane of the wave returns the same value.
+template <int NV>
+__device__ __forceinline__ double pair_sum(const double *__restrict__ partial, uint32_t first,
+                                           uint32_t count, int q) {
+    const uint32_t lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (uint32_t t = lane; t < count; t += 64) s += partial[(size_t)(first + t) * NV + q];
+    return wave_sum(s);
 }
 
 template <int NV, int B>
@@ -155,8 +175,10 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
     double *stage = F + 32;
     const unsigned nblocks = gridDim.x;
     const int npairs = a.ninst * NV;
-    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int gthreads = gridDim.x * blockDim.x;
+    // per-pair reductions: one wave per (instance, vector) pair
+    const int gwave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+    const bool lane0 = (threadIdx.x & 63) == 0;
 
     // ---- init: |v0| partials per item -----------------------------------
     for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
@@ -166,20 +188,21 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         double s[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) s[q] = 0.0;
-        if (i < d.dim)
-            for (int q = 0; q < a.nvec; ++q) {
-                const double v = d.v0[(size_t)i * a.nvec + q];
+        if (i < d.dim) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const double v = q < a.nvec ? d.v0[(size_t)i * a.nvec + q] : 0.0;
                 s[q] = v * v;
             }
+        }
         item_partials<NV>(s, stage, a.partial + (size_t)it * NV);
     }
     if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
-    for (int p = gtid; p < npairs; p += gthreads) {
+    for (int p = gwave; p < npairs; p += nwaves) {
         const InstDesc &d = a.inst[p / NV];
         const int q = p % NV;
-        double s = 0.0;
-        for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
-            s += a.partial[(size_t)it * NV + q];
+        const double s = pair_sum<NV>(a.partial, d.item_first, d.item_count, q);
+        if (!lane0) continue;
         const bool live = q < a.nvec && s > 0.0;
         a.norm0[p] = sqrt(s);
         a.scale[p] = 0.0;
@@ -279,13 +302,10 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- A': alpha per pair --------------------------------------------
-        for (int p = gtid; p < npairs; p += gthreads) {
+        for (int p = gwave; p < npairs; p += nwaves) {
             const InstDesc &d = a.inst[p / NV];
-            const int q = p % NV;
-            double s = 0.0;
-            for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
-                s += a.partial[(size_t)it * NV + q];
-            a.alpha[(size_t)p * a.steps + k] = s;
+            const double s = pair_sum<NV>(a.partial, d.item_first, d.item_count, p % NV);
+            if (lane0) a.alpha[(size_t)p * a.steps + k] = s;
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- B: w -= alpha sigma r_k; |w|^2 partials -----------------------
@@ -318,12 +338,10 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- B': beta, breakdown, next sigma / cprev -----------------------
-        for (int p = gtid; p < npairs; p += gthreads) {
+        for (int p = gwave; p < npairs; p += nwaves) {
             const InstDesc &d = a.inst[p / NV];
-            const int q = p % NV;
-            double s = 0.0;
-            for (uint32_t it = d.item_first; it < d.item_first + d.item_count; ++it)
-                s += a.partial[(size_t)it * NV + q];
+            const double s = pair_sum<NV>(a.partial, d.item_first, d.item_count, p % NV);
+            if (!lane0) continue;
             const double b = sqrt(s);
             const size_t o = (size_t)p * (a.steps + 1);
             if (a.stopped[p] != 0) {

@@ -214,8 +214,9 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             }
         }
         // bonds inside the high word: tabulated target block (own block if
-        // the bond cannot flip), same low word; the test is wave-uniform, so a
-        // bond that cannot flip skips its load with a scalar branch
+        // the bond cannot flip), same low word.  The test is wave-uniform; for
+        // FP64 a bond that cannot flip skips its load with a scalar branch, for
+        // FP32 the branch costs more than the (cached) load it saves
         for (int k = 0; k < g.nHg; ++k) {
             const BondGroup &G = gh[k];
 #pragma unroll
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) {
                     const I o = nb[m][k * kGroup + q];
-                    xj[q] = o != off[m] ? load_at(x + o, r_bytes) : xi[m];
+                    xj[q] = (sizeof(T) == 8 && o == off[m]) ? xi[m] : load_at(x + o, r_bytes);
                 }
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
