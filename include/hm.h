@@ -210,6 +210,19 @@ int hm_lanczos_ritz(hm_basis h, const double *J, const double *d_v0,
 int hm_tridiag_lowest(int32_t k, const double *alpha, const double *beta,
                       double *eval, double *evec);
 
+/* All Ritz values of a Lanczos tridiagonal and their Gauss weights (the
+ * tridiagonal eigensolve of the method's final step, here with every
+ * eigenpair).  values[j] (ascending) are the eigenvalues of the k x k matrix
+ * diag(alpha) + offdiag(beta[0..k-2]); weights[j] = z_1j^2, the squared first
+ * component of the unit eigenvector of values[j] (= |<v0|y_j>|^2 for a
+ * Lanczos run from the unit start vector v0; the weights sum to 1).  Host
+ * FP64, implicit shifted QR carrying only the first row of the eigenvector
+ * matrix.  All pointers are host arrays of k (beta: k - 1) doubles owned by
+ * the caller.  HM_EINVAL on k < 1, null or non-finite input, or no
+ * convergence. */
+int hm_tridiag_ritz(int32_t k, const double *alpha, const double *beta,
+                    double *values, double *weights);
+
 /* ---------------------------------------------------------------------------
  * Bond correlations <psi| s(u).s(v) |psi> for nb bonds (uv: host int32
  * [nb][2], 0 <= u != v < N), psi a device FP64 vector of dim entries.

@@ -6,7 +6,8 @@ HIP library (paper_0706_3293_amd): the count table, encoding, decoding,
 successor and row-gather product live in oracle/oracle.c, written from Secs. 3
 and 4 of the paper; the Lanczos recurrence, the tridiagonal eigensolve
 (scipy), the stored-basis Ritz vector and the bond correlations live in
-oracle/lanczos.py; oracle/brute.py holds independent brute-force references
+oracle/lanczos.py; magnetization sectors and thermodynamic sums live in
+oracle/sectors.py; oracle/brute.py holds independent brute-force references
 used to pin the oracle.
 
 Parity status of each function (what pins it, see tests/test_oracle_*.py):
@@ -18,6 +19,11 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
                      ferromagnet, complete graph, Majumdar-Ghosh ring)
   ground_state       pinned: dense eigenvector (|overlap| = 1), Marshall sign
   bond_correlations  pinned: dense <psi|s.s|psi>, finite differences, sum rule
+  sector_energies    pinned: saturation closed form, one-magnon Laplacian
+                     spectrum, SU(2) nesting of the sector spectra
+  exact_thermodynamics  pinned: two-site closed form, full Kronecker spectrum
+  ftl_thermodynamics pinned: exact with canonical start vectors, T -> infinity
+                     sum rule, T -> 0 limit
 """
 from .core import Subspace, count, count_table, max_threads  # noqa: F401
 from .lanczos import (bond_correlations, ground_state, lanczos,  # noqa: F401

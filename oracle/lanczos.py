@@ -19,7 +19,9 @@ Paige's ordering, in FP64:
 
 E0 is the smallest eigenvalue of the k x k tridiagonal matrix with diagonal
 alpha_1..alpha_k and off-diagonal beta_1..beta_{k-1}; the library routine
-scipy.linalg.eigh_tridiagonal (LAPACK) serves as that step.  The ground-state
+scipy.linalg.eigh_tridiagonal (LAPACK's implicit QL/QR driver stev, which
+also copes with the near-repeated Ritz values of runs continued past
+convergence) serves as that step.  The ground-state
 vector is the Ritz vector V_k c from the *stored* Krylov basis, and bond
 correlations <psi| s(u).s(v) |psi> come from the oracle's own H x with a
 coupling matrix that has a single entry J_uv = -1 (then H = s(u).s(v) by
@@ -81,7 +83,7 @@ def ritz(alpha, beta, which: int = 0):
     off = np.asarray(beta, dtype=np.float64)[: k - 1]
     if k == 1:
         return float(alpha[0]), np.ones(1)
-    w, z = scipy.linalg.eigh_tridiagonal(alpha, off)
+    w, z = scipy.linalg.eigh_tridiagonal(alpha, off, lapack_driver="stev")
     return float(w[which]), z[:, which].copy()
 
 
@@ -92,7 +94,7 @@ def ritz_all(alpha, beta):
     if k == 1:
         return alpha.copy(), np.ones(1)
     w, z = scipy.linalg.eigh_tridiagonal(
-        alpha, np.asarray(beta, dtype=np.float64)[: k - 1])
+        alpha, np.asarray(beta, dtype=np.float64)[: k - 1], lapack_driver="stev")
     return w, z[0, :] ** 2
 
 

@@ -7,7 +7,12 @@ include/hm.h); this package is its thin Python binding:
                    Lanczos, ground-state recompute, bond correlations
   GroundStateEnergy  torch.autograd.Function for E0(J) with dE0/dJ = -<s.s>
   lanczos_batched  many instances and start vectors in one persistent launch
+  magnetization_curve, ftl_thermodynamics
+                   E0(M) over all sectors and finite-temperature Lanczos sums
 """
-from .api import Basis, LanczosResult, count, last_timing, set_timing, tridiag_lowest  # noqa: F401
+from .api import (Basis, LanczosResult, count, last_timing, set_timing,  # noqa: F401
+                  tridiag_lowest, tridiag_ritz)
 from .autograd import GroundStateEnergy, ground_state, ground_state_energy  # noqa: F401,E402
 from .batched import BatchedProblem, BatchedResult, lanczos_batched  # noqa: F401,E402
+from .sectors import (MagnetizationCurve, ftl_thermodynamics,  # noqa: F401,E402
+                      magnetization_curve)

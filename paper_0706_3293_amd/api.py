@@ -217,6 +217,19 @@ def tridiag_lowest(alpha, beta):
     return ev.value, vec
 
 
+def tridiag_ritz(alpha, beta):
+    """All eigenvalues of tridiag(alpha; beta[:k-1]) (ascending) and the squared
+    first components of their unit eigenvectors, by the library's host solver."""
+    alpha, ap = _host_dbl(alpha)
+    k = alpha.shape[0]
+    beta, bp = _host_dbl(np.concatenate([np.asarray(beta, dtype=np.float64)[: k - 1], [0.0]]))
+    vals = np.zeros(k)
+    wts = np.zeros(k)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().hm_tridiag_ritz(k, ap, bp, vals.ctypes.data_as(dp), wts.ctypes.data_as(dp)))
+    return vals, wts
+
+
 def set_timing(enable: bool):
     lib().hm_set_timing(int(bool(enable)))
 

@@ -7,7 +7,7 @@ import numpy as np
 import torch
 
 from ._lib import check, lib
-from .api import _stream
+from .api import _stream, tridiag_ritz
 
 
 @dataclass
@@ -19,13 +19,8 @@ class BatchedResult:
 
     def ritz(self, k, r):
         """Ritz values and first-component weights |z_1|^2 of pair (k, r)."""
-        import scipy.linalg
         n = int(self.steps_done[k, r])
-        a, b = self.alpha[k, r, :n], self.beta[k, r, : max(n - 1, 0)]
-        if n == 1:
-            return a.copy(), np.ones(1)
-        w, z = scipy.linalg.eigh_tridiagonal(a, b)
-        return w, z[0] ** 2
+        return tridiag_ritz(self.alpha[k, r, :n], self.beta[k, r, : max(n - 1, 0)])
 
 
 class BatchedProblem:

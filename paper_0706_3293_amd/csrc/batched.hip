@@ -262,28 +262,42 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
 #pragma unroll
                 for (int q = 0; q < NV; ++q) acc[q] = 0.0f;
                 float diag = 0.0f;
-                for (int b = 0; b < d.nb; ++b) {
-                    const int u = d.bonds[b].u, v = d.bonds[b].v;
-                    const float mJ4 = (float)d.bonds[b].mJ4;
-                    const double mJ2 = d.bonds[b].mJ2;
-                    const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
-                    diag += mJ4 * (float)((d.two_s - 2 * au) * (d.two_s - 2 * av));
-                    if (au >= 1 && av < d.two_s) {
-                        const uint32_t j = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
-                        const float c = (float)(mJ2 * F[au] * F[av + 1]);
-                        float xj[NV];
-                        load_row<NV>(xr + (size_t)j * NV, xj);
+                // moves in batches: targets and coefficients first (a move that
+                // is not allowed reads the own row with coefficient 0), then all
+                // row loads of the batch, then the products, so kMoves row
+                // gathers are in flight together
+                constexpr int kMoves = NV >= 16 ? 4 : (NV >= 8 ? 8 : 16);
+                for (int b0 = 0; b0 < d.nb; b0 += kMoves / 2) {
+                    uint32_t jm[kMoves];
+                    float cm[kMoves];
 #pragma unroll
-                        for (int q = 0; q < NV; ++q) acc[q] += c * xj[q];
+                    for (int t = 0; t < kMoves / 2; ++t) {
+                        jm[2 * t] = jm[2 * t + 1] = i;
+                        cm[2 * t] = cm[2 * t + 1] = 0.0f;
+                        const int b = b0 + t;
+                        if (b < d.nb) {
+                            const int u = d.bonds[b].u, v = d.bonds[b].v;
+                            const double mJ2 = d.bonds[b].mJ2;
+                            const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
+                            diag += (float)d.bonds[b].mJ4 *
+                                    (float)((d.two_s - 2 * au) * (d.two_s - 2 * av));
+                            if (au >= 1 && av < d.two_s) {
+                                jm[2 * t] = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
+                                cm[2 * t] = (float)(mJ2 * F[au] * F[av + 1]);
+                            }
+                            if (av >= 1 && au < d.two_s) {
+                                jm[2 * t + 1] = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
+                                cm[2 * t + 1] = (float)(mJ2 * F[av] * F[au + 1]);
+                            }
+                        }
                     }
-                    if (av >= 1 && au < d.two_s) {
-                        const uint32_t j = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
-                        const float c = (float)(mJ2 * F[av] * F[au + 1]);
-                        float xj[NV];
-                        load_row<NV>(xr + (size_t)j * NV, xj);
+                    float xj[kMoves][NV];
 #pragma unroll
-                        for (int q = 0; q < NV; ++q) acc[q] += c * xj[q];
-                    }
+                    for (int m = 0; m < kMoves; ++m) load_row<NV>(xr + (size_t)jm[m] * NV, xj[m]);
+#pragma unroll
+                    for (int m = 0; m < kMoves; ++m)
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) acc[q] += cm[m] * xj[m][q];
                 }
                 float prv[NV];
                 if (k > 0) load_row<NV>(rp + ((size_t)d.vec_off + i) * NV, prv);

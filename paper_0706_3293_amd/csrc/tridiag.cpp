@@ -1,0 +1,103 @@
+// Ritz values and Gauss weights of a Lanczos tridiagonal on the host (FP64).
+//
+// All eigenvalues of T = diag(alpha) + offdiag(beta) and the squared first
+// components of their unit eigenvectors.  For a Lanczos run from a unit start
+// vector v0 these are the Ritz values theta_j and the weights |<v0|y_j>|^2
+// of the Krylov quadrature sum_j w_j f(theta_j) ~ <v0|f(H)|v0> that
+// finite-temperature Lanczos sums are built from.
+//
+// Method: implicit symmetric QR with Wilkinson shifts (bulge chasing with
+// Givens rotations), deflating converged off-diagonals from the bottom; only
+// the first row of the accumulated rotation matrix is carried, as Golub and
+// Welsch do for Gauss quadrature (Math. Comp. 23, 1969).
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+
+// One implicit shifted QR step on the unreduced block [l, m] of (d, e):
+// e[i] couples i and i + 1.  z is the first row of the rotation product.
+void qr_step(std::vector<double> &d, std::vector<double> &e, std::vector<double> &z, int l,
+             int m) {
+    // Wilkinson shift: eigenvalue of the trailing 2x2 block nearer d[m]
+    const double a = d[m - 1], b = d[m], f = e[m - 1];
+    const double delta = 0.5 * (a - b);
+    const double sgn = delta >= 0.0 ? 1.0 : -1.0;
+    const double mu = b - f * f / (delta + sgn * std::hypot(delta, f));
+    // first rotation from the shifted first column, then chase the bulge
+    double x = d[l] - mu, y = e[l];
+    for (int k = l; k < m; ++k) {
+        const double r = std::hypot(x, y);
+        const double c = r == 0.0 ? 1.0 : x / r;
+        const double s = r == 0.0 ? 0.0 : -y / r;
+        if (k > l) e[k - 1] = r;   // the bulge at (k-1, k+1) is annihilated
+        const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+        // new basis q_k' = c q_k - s q_{k+1}, q_{k+1}' = s q_k + c q_{k+1}
+        d[k] = c * c * dk - 2.0 * c * s * ek + s * s * dk1;
+        d[k + 1] = s * s * dk + 2.0 * c * s * ek + c * c * dk1;
+        e[k] = c * s * (dk - dk1) + (c * c - s * s) * ek;
+        if (k + 1 < m) {
+            x = e[k];
+            y = -s * e[k + 1];     // the new bulge at (k, k+2)
+            e[k + 1] *= c;
+        }
+        const double z0 = z[k], z1 = z[k + 1];
+        z[k] = c * z0 - s * z1;
+        z[k + 1] = s * z0 + c * z1;
+    }
+}
+
+bool negligible(const std::vector<double> &d, const std::vector<double> &e, int i) {
+    return std::fabs(e[i]) <= DBL_EPSILON * (std::fabs(d[i]) + std::fabs(d[i + 1]));
+}
+
+}  // namespace
+
+int tridiag_ritz(int k, const double *alpha, const double *beta, double *values,
+                 double *weights) {
+    if (k < 1) return fail(HM_EINVAL, "k must be >= 1");
+    if (!alpha || !values || !weights || (k > 1 && !beta)) return fail(HM_EINVAL, "null argument");
+    std::vector<double> d(alpha, alpha + k), e(k, 0.0), z(k, 0.0);
+    for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
+    for (int i = 0; i < k; ++i)
+        if (!std::isfinite(d[i]) || !std::isfinite(e[i]))
+            return fail(HM_EINVAL, "alpha/beta must be finite");
+    z[0] = 1.0;
+    int m = k - 1, iter = 0;
+    const int max_iter = 60 * k;
+    while (m > 0) {
+        if (negligible(d, e, m - 1)) {
+            e[m - 1] = 0.0;
+            --m;
+            continue;
+        }
+        int l = m - 1;
+        while (l > 0 && !negligible(d, e, l - 1)) --l;
+        if (l > 0) e[l - 1] = 0.0;
+        if (++iter > max_iter) return fail(HM_EINVAL, "tridiagonal QR did not converge");
+        qr_step(d, e, z, l, m);
+    }
+    std::vector<int> order(k);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
+    for (int j = 0; j < k; ++j) {
+        values[j] = d[order[j]];
+        weights[j] = z[order[j]] * z[order[j]];
+    }
+    return HM_OK;
+}
+
+}  // namespace hm
+
+extern "C" int hm_tridiag_ritz(int32_t k, const double *alpha, const double *beta,
+                               double *values, double *weights) {
+    hm::clear_error();
+    return hm::tridiag_ritz(k, alpha, beta, values, weights);
+}

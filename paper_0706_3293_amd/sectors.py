@@ -1,0 +1,120 @@
+"""Magnetization curve E0(M) and finite-temperature Lanczos thermodynamics.
+
+H conserves the total S^z = M, which is why the paper works in the sectors
+H(M) (Sec. 2); a magnetization curve needs the lowest energy of each one.  By
+the spin-flip symmetry a_u -> 2s - a_u the sectors M and -M share their
+spectrum, so only M >= 0 (A = Ns - M = 0 .. floor(Ns)) is computed.
+
+Every sector of one coupling matrix is one instance of the batched persistent
+Lanczos (hm_lanczos_batched): all sectors and start vectors run in a single
+launch.  For finite temperature, each (sector, start vector) run gives Ritz
+values theta_j and Gauss weights |<r|y_j>|^2 (hm_tridiag_ritz), and
+
+    Z_M ~ (D_M / R) sum_r sum_j |<r|y_j>|^2 exp(-theta_j / T)
+
+(likewise for <H> and <H^2>) with R random unit start vectors per sector;
+sectors M > 0 count twice.  The host keeps only these Boltzmann sums.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .api import Basis
+from .batched import BatchedProblem
+
+
+def sector_two_M(N: int, two_s: int):
+    """2M of every sector with M >= 0, from the saturated one down."""
+    top = N * two_s
+    return list(range(top, -1, -2))
+
+
+def sector_bases(N: int, two_s: int):
+    return [Basis(N, two_s=two_s, two_M=tm) for tm in sector_two_M(N, two_s)]
+
+
+def multiplicity(two_M: int) -> int:
+    return 1 if two_M == 0 else 2
+
+
+def random_start_vectors(bases, nvec: int, seed: int = 0):
+    """uniform[-1, 1) FP64 start vectors (nvec x dim) per basis, on the device.
+
+    Sector k draws from torch's CUDA generator seeded with seed + k.
+    """
+    out = []
+    for k, b in enumerate(bases):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(seed) + k)
+        v = torch.rand((nvec, b.dim), generator=g, dtype=torch.float64, device="cuda")
+        out.append(v.mul_(2.0).sub_(1.0))
+    return out
+
+
+@dataclass
+class MagnetizationCurve:
+    two_M: np.ndarray        # [sectors], descending
+    dim: np.ndarray          # [sectors]
+    E0: np.ndarray           # [sectors]: lowest over the start vectors
+    E0_runs: np.ndarray      # [sectors][nvec]
+    steps_done: np.ndarray   # [sectors][nvec]
+
+
+def _run(N, two_s, J, steps, nvec, seed, V0s, tol):
+    bases = sector_bases(N, two_s)
+    if V0s is None:
+        V0s = random_start_vectors(bases, nvec, seed)
+    if len(V0s) != len(bases):
+        raise ValueError(f"need start vectors for {len(bases)} sectors")
+    J = np.asarray(J, dtype=np.float64)
+    res = BatchedProblem(bases, [J] * len(bases), V0s, steps, tol).run()
+    return bases, res
+
+
+def magnetization_curve(N: int, two_s: int, J, steps: int, nvec: int = 1, seed: int = 0,
+                        V0s=None, tol: float = 0.0) -> MagnetizationCurve:
+    """E0 of every sector M >= 0 in one batched launch (FP32 vectors, FP64
+    coefficients).  V0s: optional list of (nvec, dim) start vectors per sector
+    in the order of sector_two_M."""
+    bases, res = _run(N, two_s, J, steps, nvec, seed, V0s, tol)
+    return MagnetizationCurve(
+        two_M=np.array(sector_two_M(N, two_s)),
+        dim=np.array([b.dim for b in bases], dtype=np.int64),
+        E0=res.E0.min(axis=1), E0_runs=res.E0, steps_done=res.steps_done)
+
+
+def thermo_sums(levels, weights, temps):
+    """Z (relative to exp(-E_min / T)), <H> and C = (<H^2> - <H>^2) / T^2."""
+    levels = np.asarray(levels, dtype=np.float64)
+    weights = np.asarray(weights, dtype=np.float64)
+    temps = np.asarray(temps, dtype=np.float64)
+    e_min = levels.min()
+    b = np.exp(-(levels[None, :] - e_min) / temps[:, None]) * weights[None, :]
+    Z = b.sum(axis=1)
+    E = (b * levels).sum(axis=1) / Z
+    E2 = (b * levels ** 2).sum(axis=1) / Z
+    return {"T": temps, "E_min": e_min, "Z": Z, "E": E, "C": (E2 - E * E) / temps ** 2}
+
+
+def ftl_thermodynamics(N: int, two_s: int, J, temps, steps: int, nvec: int = 16,
+                       seed: int = 0, V0s=None, tol: float = 0.0):
+    """Finite-temperature Lanczos Z(T), E(T), C(T) over all sectors (k_B = 1).
+
+    Returns the sums of thermo_sums plus the levels and weights they came
+    from and the dimension the weights add up to at T -> infinity."""
+    bases, res = _run(N, two_s, J, steps, nvec, seed, V0s, tol)
+    levels, weights = [], []
+    for k, (b, tm) in enumerate(zip(bases, sector_two_M(N, two_s))):
+        scale = multiplicity(tm) * b.dim / nvec
+        for r in range(nvec):
+            th, w = res.ritz(k, r)
+            levels.append(th)
+            weights.append(w * scale)
+    levels = np.concatenate(levels)
+    weights = np.concatenate(weights)
+    out = thermo_sums(levels, weights, temps)
+    out.update(levels=levels, weights=weights,
+               total_dim=sum(multiplicity(tm) * b.dim
+                             for b, tm in zip(bases, sector_two_M(N, two_s))))
+    return out

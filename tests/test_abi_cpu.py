@@ -108,6 +108,43 @@ def test_error_paths(L):
     assert abs(abs(vec @ z[:, 0]) - 1) < 1e-10
 
 
+@pytest.mark.parametrize("k", [1, 2, 5, 40, 300])
+def test_tridiag_ritz_matches_lapack(k):
+    # all Ritz values and Gauss weights vs LAPACK's tridiagonal eigensolver
+    import scipy.linalg
+    from paper_0706_3293_amd import tridiag_ritz
+    rng = np.random.default_rng(k)
+    a, b = rng.normal(size=k), rng.uniform(0.05, 1, max(k - 1, 0))
+    vals, wts = tridiag_ritz(a, b)
+    if k == 1:
+        assert vals[0] == a[0] and wts[0] == 1.0
+        return
+    w, z = scipy.linalg.eigh_tridiagonal(a, b, lapack_driver="stev")
+    scale = np.abs(a).max() + 2 * b.max()
+    assert np.abs(vals - w).max() <= 1e-13 * k * scale
+    assert np.abs(wts - z[0] ** 2).max() <= 1e-12
+    assert abs(wts.sum() - 1.0) < 1e-13
+
+
+def test_tridiag_ritz_decoupled_and_degenerate_blocks(L):
+    # beta = 0 splits T; the start vector only sees the first block, so the
+    # other blocks' eigenvalues get weight 0; repeated eigenvalues stay finite
+    from paper_0706_3293_amd import tridiag_ritz
+    a = np.array([2.0, 2.0, -1.0, 3.0, 3.0])
+    b = np.array([1.0, 0.0, 0.5, 0.0])
+    vals, wts = tridiag_ritz(a, b)
+    want = np.sort(np.concatenate([[1.0, 3.0], np.linalg.eigvalsh([[-1.0, 0.5], [0.5, 3.0]]),
+                                   [3.0]]))
+    assert np.abs(vals - want).max() < 1e-14
+    w_first = {1.0: 0.5, 3.0: 0.5}
+    assert abs(wts.sum() - 1.0) < 1e-15
+    assert abs(wts[np.argmin(np.abs(vals - 1.0))] - w_first[1.0]) < 1e-14
+    assert L.hm_tridiag_ritz(0, None, None, None, None) == -1
+    nan = np.array([np.nan, 1.0])
+    p = nan.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert L.hm_tridiag_ritz(2, p, p, p, p) == -1
+
+
 def test_half_integer_arguments():
     from fractions import Fraction
     from paper_0706_3293_amd import Basis
