@@ -48,6 +48,9 @@ def parse():
                     help="also time a 1 GiB device copy (profiling reference)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the timings of the other workloads")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="only time the other workloads (a profiling mode: prints "
+                         "{\"other_workloads\": ...}, not the benchmark line)")
     return ap.parse_args()
 
 
@@ -129,6 +132,28 @@ def extras():
         ms=1e3 * dt, instances=64, vectors=16, steps=80, rows=prob.rows,
         row_vector_steps_per_s=prob.rows * 16 * 80 / dt,
         E0_spread_max=float(np.max(np.ptp(r.E0, axis=1))))
+    # magnetization curve of the N=24 J1-J2 ring: 13 sectors M >= 0, 2 start
+    # vectors each, 150 steps, one launch; then finite-temperature Lanczos of
+    # the N=20 ring, 11 sectors x 16 vectors x 60 steps
+    from paper_0706_3293_amd import ftl_thermodynamics, magnetization_curve
+    J24 = inputs.ring_couplings(24, -1.0, -0.25)
+    magnetization_curve(24, 1, J24, 150, nvec=2, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c = magnetization_curve(24, 1, J24, 150, nvec=2, seed=0)
+    dt = time.perf_counter() - t0
+    out["magnetization_curve_ring24"] = dict(
+        ms=1e3 * dt, sectors=len(c.two_M), rows=int(c.dim.sum()), vectors=2, steps=150,
+        E0=[float(e) for e in c.E0])
+    J20 = inputs.ring_couplings(20, -1.0, -0.25)
+    temps = [0.1, 0.25, 0.5, 1.0, 2.0, 4.0]
+    ftl_thermodynamics(20, 1, J20, temps, 60, nvec=16, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = ftl_thermodynamics(20, 1, J20, temps, 60, nvec=16, seed=0)
+    dt = time.perf_counter() - t0
+    out["ftl_ring20"] = dict(ms=1e3 * dt, sectors=11, vectors=16, steps=60, T=temps,
+                             E=[float(e) for e in th["E"]], C=[float(x) for x in th["C"]])
     return out
 
 
@@ -143,6 +168,9 @@ def main():
     from paper_0706_3293_amd import Basis, api, autotune, inputs
 
     torch.cuda.set_device(0)
+    if args.extras_only:
+        print(json.dumps({"other_workloads": extras()}), flush=True)
+        return
     w = inputs.WORKLOADS[args.workload]
     N = w["N"]
     J = inputs.workload_couplings(args.workload)

@@ -13,8 +13,9 @@
 //             partials in a fixed order
 //         B:  w -= alpha sigma r, |w|^2 partials
 //         B': beta, breakdown test, sigma and cprev of the next step
-// Work items are 256-row tiles of one instance; workgroups are persistent and
-// walk the items in a fixed order, so every sum has a fixed order.  The grid
+// Work items are 256-row tiles of one instance; persistent workgroups take
+// chunks of consecutive items in a fixed order and reduce once per run of
+// items of one instance, so every sum has a fixed order for a given grid.  The grid
 // barrier is a counter and a generation word with a bounded spin: a wave that
 // waits too long raises an abort flag and every wave leaves the kernel.
 #include <algorithm>
@@ -46,6 +47,15 @@ struct Item {
     uint32_t inst, row0;
 };
 
+// A bond as the pass-A loop reads it from LDS: sites packed u | v << 16.
+struct LdsBond {
+    int32_t uv;
+    float mJ4;
+    double mJ2;
+};
+constexpr int kStageWaves = 16;   // per-wave partial slots (workgroup <= 1024 threads)
+constexpr int kChunk = 4;         // items a workgroup takes at a time
+
 struct GridBar {
     unsigned count, gen;
     int abort;
@@ -65,6 +75,7 @@ struct BatchArgs {
     double *scale, *norm0;     // [npairs]
     int *stopped;              // [npairs]: steps done at breakdown, 0 while running
     int max_prefix;            // entries of the largest prefix table
+    int max_bonds;             // bonds of the largest coupling list
 };
 
 // Grid-wide barrier; returns false if the run was aborted (timeout).
@@ -170,32 +181,64 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int ok_flag;
     __shared__ double sc_sigma[NV], sc_c[NV], sc_a[NV];
+    // instance in LDS (pass A): the kernel writes through pointers that may
+    // alias the descriptors, so uniform reads of them from global memory
+    // would be vector loads per lane; LDS broadcasts are cheap
+    __shared__ int s_N, s_A, s_two_s, s_nb;
+    __shared__ uint32_t s_dim, s_vec_off, s_item_end;
+    __shared__ uint32_t sb_dim, sb_vec_off, sb_item_end;   // pass B's instance
     uint32_t *P = reinterpret_cast<uint32_t *>(smem);
     double *F = reinterpret_cast<double *>(smem + ((a.max_prefix * 4 + 15) / 16) * 16);
     double *stage = F + 32;
+    LdsBond *Bd = reinterpret_cast<LdsBond *>(stage + kStageWaves * NV);
     const unsigned nblocks = gridDim.x;
     const int npairs = a.ninst * NV;
     // per-pair reductions: one wave per (instance, vector) pair
     const int gwave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
     const bool lane0 = (threadIdx.x & 63) == 0;
+    // Workgroups take chunks of kChunk consecutive items, chunk c going to
+    // workgroup c % grid, so the grid sweeps the items roughly in order (a
+    // narrow working set for the gathers).  Within a chunk, consecutive items
+    // of one instance form a segment: threads add their rows' FP64
+    // contributions over the segment and the workgroup reduces once per
+    // segment, into the slot of the segment's first item.  All other slots
+    // stay zero, so the per-pair sums over an instance's slots keep a fixed
+    // order for a given grid.
+    const int n_chunks = (a.n_items + kChunk - 1) / kChunk;
+    for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
+        for (int t = threadIdx.x; t < (i1 - i0) * NV; t += blockDim.x)
+            a.partial[(size_t)i0 * NV + t] = 0.0;
+    }
 
-    // ---- init: |v0| partials per item -----------------------------------
-    for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-        const Item itm = a.items[it];
-        const InstDesc &d = a.inst[itm.inst];
-        const uint32_t i = itm.row0 + threadIdx.x;
+    // ---- init: |v0| partials per segment --------------------------------
+    {
         double s[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) s[q] = 0.0;
-        if (i < d.dim) {
-#pragma unroll
-            for (int q = 0; q < NV; ++q) {
-                const double v = q < a.nvec ? d.v0[(size_t)i * a.nvec + q] : 0.0;
-                s[q] = v * v;
+        for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+            const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
+            int seg = i0;
+            for (int it = i0; it < i1; ++it) {
+                const Item itm = a.items[it];
+                const InstDesc &d = a.inst[itm.inst];
+                const uint32_t i = itm.row0 + threadIdx.x;
+                if (i < d.dim) {
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        const double v = q < a.nvec ? d.v0[(size_t)i * a.nvec + q] : 0.0;
+                        s[q] += v * v;
+                    }
+                }
+                if (it + 1 == i1 || (uint32_t)(it + 1) == d.item_first + d.item_count) {
+                    item_partials<NV>(s, stage, a.partial + (size_t)seg * NV);
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) s[q] = 0.0;
+                    seg = it + 1;
+                }
             }
         }
-        item_partials<NV>(s, stage, a.partial + (size_t)it * NV);
     }
     if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
     for (int p = gwave; p < npairs; p += nwaves) {
@@ -234,85 +277,120 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         const float *__restrict__ rp = a.r[(k + 2) % 3];
         float *__restrict__ w = a.r[(k + 1) % 3];
         // ---- A: w = sigma H r_k - cprev r_{k-1}; alpha partials ----------
-        for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-            const Item itm = a.items[it];
-            const InstDesc &d = a.inst[itm.inst];
-            if ((int)itm.inst != loaded) {
-                const int plen = d.N * (d.A + 1) * (d.two_s + 1);
-                for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = d.prefix[t];
-                for (int t = threadIdx.x; t < d.two_s + 2; t += blockDim.x) F[t] = d.ladder[t];
-                loaded = itm.inst;
-            }
-            if (threadIdx.x < NV) {
-                const int p = itm.inst * NV + threadIdx.x;
-                sc_sigma[threadIdx.x] = a.sigma[(size_t)p * (a.steps + 1) + k];
-                sc_c[threadIdx.x] = a.cprev[(size_t)p * (a.steps + 1) + k];
-            }
-            __syncthreads();
-            const Prefix<uint32_t> pv{P, d.A + 1, d.two_s + 1};
-            const uint32_t i = itm.row0 + threadIdx.x;
-            double dots[NV];
+        double dacc[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) dots[q] = 0.0;
-            if (i < d.dim) {
-                const float *__restrict__ xr = rk + (size_t)d.vec_off * NV;
-                const uint64_t st = unrank_state<uint32_t, B>(i, pv, d.N, d.A, d.two_s);
-                float xi[NV], acc[NV];
-                load_row<NV>(xr + (size_t)i * NV, xi);
-#pragma unroll
-                for (int q = 0; q < NV; ++q) acc[q] = 0.0f;
-                float diag = 0.0f;
-                // moves in batches: targets and coefficients first (a move that
-                // is not allowed reads the own row with coefficient 0), then all
-                // row loads of the batch, then the products, so kMoves row
-                // gathers are in flight together
-                constexpr int kMoves = NV >= 16 ? 4 : (NV >= 8 ? 8 : 16);
-                for (int b0 = 0; b0 < d.nb; b0 += kMoves / 2) {
-                    uint32_t jm[kMoves];
-                    float cm[kMoves];
-#pragma unroll
-                    for (int t = 0; t < kMoves / 2; ++t) {
-                        jm[2 * t] = jm[2 * t + 1] = i;
-                        cm[2 * t] = cm[2 * t + 1] = 0.0f;
-                        const int b = b0 + t;
-                        if (b < d.nb) {
-                            const int u = d.bonds[b].u, v = d.bonds[b].v;
-                            const double mJ2 = d.bonds[b].mJ2;
-                            const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
-                            diag += (float)d.bonds[b].mJ4 *
-                                    (float)((d.two_s - 2 * au) * (d.two_s - 2 * av));
-                            if (au >= 1 && av < d.two_s) {
-                                jm[2 * t] = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
-                                cm[2 * t] = (float)(mJ2 * F[au] * F[av + 1]);
-                            }
-                            if (av >= 1 && au < d.two_s) {
-                                jm[2 * t + 1] = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
-                                cm[2 * t + 1] = (float)(mJ2 * F[av] * F[au + 1]);
+        for (int q = 0; q < NV; ++q) dacc[q] = 0.0;
+        int sc_loaded = -1;
+        for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+            const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
+            int seg = i0;
+            for (int it = i0; it < i1; ++it) {
+                const Item itm = a.items[it];
+                // a new instance starts a segment; the previous segment ended with
+                // a workgroup barrier, so nobody still reads what is replaced here
+                if ((int)itm.inst != sc_loaded) {
+                    if ((int)itm.inst != loaded) {
+                        const InstDesc &d = a.inst[itm.inst];
+                        const int plen = d.N * (d.A + 1) * (d.two_s + 1);
+                        for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = d.prefix[t];
+                        for (int t = threadIdx.x; t < d.two_s + 2; t += blockDim.x) F[t] = d.ladder[t];
+                        for (int t = threadIdx.x; t < d.nb; t += blockDim.x) {
+                            const BondDev bd = d.bonds[t];
+                            Bd[t] = LdsBond{bd.u | (bd.v << 16), (float)bd.mJ4, bd.mJ2};
+                        }
+                        if (threadIdx.x == 0) {
+                            s_N = d.N;
+                            s_A = d.A;
+                            s_two_s = d.two_s;
+                            s_nb = d.nb;
+                            s_dim = d.dim;
+                            s_vec_off = d.vec_off;
+                            s_item_end = d.item_first + d.item_count;
+                        }
+                        loaded = itm.inst;
+                    }
+                    if (threadIdx.x < NV) {
+                        const int p = itm.inst * NV + threadIdx.x;
+                        sc_sigma[threadIdx.x] = a.sigma[(size_t)p * (a.steps + 1) + k];
+                        sc_c[threadIdx.x] = a.cprev[(size_t)p * (a.steps + 1) + k];
+                    }
+                    sc_loaded = itm.inst;
+                    __syncthreads();
+                }
+                const int iN = __builtin_amdgcn_readfirstlane(s_N);
+                const int iA = __builtin_amdgcn_readfirstlane(s_A);
+                const int two_s = __builtin_amdgcn_readfirstlane(s_two_s);
+                const int nb = __builtin_amdgcn_readfirstlane(s_nb);
+                const uint32_t dim = __builtin_amdgcn_readfirstlane(s_dim);
+                const uint32_t vec_off = __builtin_amdgcn_readfirstlane(s_vec_off);
+                const uint32_t item_end = __builtin_amdgcn_readfirstlane(s_item_end);
+                const Prefix<uint32_t> pv{P, iA + 1, two_s + 1};
+                const uint32_t i = itm.row0 + threadIdx.x;
+                if (i < dim) {
+                    const float *__restrict__ xr = rk + (size_t)vec_off * NV;
+                    const uint64_t st = unrank_state<uint32_t, B>(i, pv, iN, iA, two_s);
+                    float xi[NV], acc[NV];
+                    load_row<NV>(xr + (size_t)i * NV, xi);
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) acc[q] = 0.0f;
+                    float diag = 0.0f;
+                    // moves in batches: targets and coefficients first (a move that
+                    // is not allowed reads the own row with coefficient 0), then all
+                    // row loads of the batch, then the products, so kMoves row
+                    // gathers are in flight together
+                    constexpr int kMoves = NV >= 16 ? 4 : (NV >= 8 ? 8 : 16);
+                    for (int b0 = 0; b0 < nb; b0 += kMoves / 2) {
+                        uint32_t jm[kMoves];
+                        float cm[kMoves];
+    #pragma unroll
+                        for (int t = 0; t < kMoves / 2; ++t) {
+                            jm[2 * t] = jm[2 * t + 1] = i;
+                            cm[2 * t] = cm[2 * t + 1] = 0.0f;
+                            const int b = b0 + t;
+                            if (b < nb) {
+                                const LdsBond bd = Bd[b];
+                                const int u = bd.uv & 0xffff, v = bd.uv >> 16;
+                                const double mJ2 = bd.mJ2;
+                                const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
+                                diag += bd.mJ4 * (float)((two_s - 2 * au) * (two_s - 2 * av));
+                                if (au >= 1 && av < two_s) {
+                                    jm[2 * t] = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
+                                    cm[2 * t] = (float)(mJ2 * F[au] * F[av + 1]);
+                                }
+                                if (av >= 1 && au < two_s) {
+                                    jm[2 * t + 1] = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
+                                    cm[2 * t + 1] = (float)(mJ2 * F[av] * F[au + 1]);
+                                }
                             }
                         }
+                        float xj[kMoves][NV];
+    #pragma unroll
+                        for (int m = 0; m < kMoves; ++m) load_row<NV>(xr + (size_t)jm[m] * NV, xj[m]);
+    #pragma unroll
+                        for (int m = 0; m < kMoves; ++m)
+    #pragma unroll
+                            for (int q = 0; q < NV; ++q) acc[q] += cm[m] * xj[m][q];
                     }
-                    float xj[kMoves][NV];
-#pragma unroll
-                    for (int m = 0; m < kMoves; ++m) load_row<NV>(xr + (size_t)jm[m] * NV, xj[m]);
-#pragma unroll
-                    for (int m = 0; m < kMoves; ++m)
-#pragma unroll
-                        for (int q = 0; q < NV; ++q) acc[q] += cm[m] * xj[m][q];
+                    float prv[NV];
+                    if (k > 0) load_row<NV>(rp + ((size_t)vec_off + i) * NV, prv);
+                    float out[NV];
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        const double hv = (double)(diag * xi[q] + acc[q]);
+                        double wq = sc_sigma[q] * hv;
+                        if (k > 0) wq -= sc_c[q] * (double)prv[q];
+                        out[q] = (float)wq;
+                        dacc[q] += (double)out[q] * (sc_sigma[q] * (double)xi[q]);
+                    }
+                    store_row<NV>(w + ((size_t)vec_off + i) * NV, out);
                 }
-                float prv[NV];
-                if (k > 0) load_row<NV>(rp + ((size_t)d.vec_off + i) * NV, prv);
-                float out[NV];
-#pragma unroll
-                for (int q = 0; q < NV; ++q) {
-                    const double hv = (double)(diag * xi[q] + acc[q]);
-                    double wq = sc_sigma[q] * hv;
-                    if (k > 0) wq -= sc_c[q] * (double)prv[q];
-                    out[q] = (float)wq;
-                    dots[q] = (double)out[q] * (sc_sigma[q] * (double)xi[q]);
+                if (it + 1 == i1 || (uint32_t)(it + 1) == item_end) {
+                    item_partials<NV>(dacc, stage, a.partial + (size_t)seg * NV);
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) dacc[q] = 0.0;
+                    seg = it + 1;
                 }
-                store_row<NV>(w + ((size_t)d.vec_off + i) * NV, out);
             }
-            item_partials<NV>(dots, stage, a.partial + (size_t)it * NV);
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- A': alpha per pair --------------------------------------------
@@ -323,32 +401,53 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- B: w -= alpha sigma r_k; |w|^2 partials -----------------------
-        for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-            const Item itm = a.items[it];
-            const InstDesc &d = a.inst[itm.inst];
-            if (threadIdx.x < NV) {
-                const int p = itm.inst * NV + threadIdx.x;
-                sc_a[threadIdx.x] = a.alpha[(size_t)p * a.steps + k] *
-                                    a.sigma[(size_t)p * (a.steps + 1) + k];
-            }
-            __syncthreads();
-            const uint32_t i = itm.row0 + threadIdx.x;
-            double ss[NV];
+        double ss[NV];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) ss[q] = 0.0;
-            if (i < d.dim) {
-                const size_t row = ((size_t)d.vec_off + i) * NV;
-                float wv[NV], rv[NV];
-                load_row<NV>(w + row, wv);
-                load_row<NV>(rk + row, rv);
-#pragma unroll
-                for (int q = 0; q < NV; ++q) {
-                    wv[q] = (float)((double)wv[q] - sc_a[q] * (double)rv[q]);
-                    ss[q] = (double)wv[q] * (double)wv[q];
+        for (int q = 0; q < NV; ++q) ss[q] = 0.0;
+        sc_loaded = -1;
+        for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+            const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
+            int seg = i0;
+            for (int it = i0; it < i1; ++it) {
+                const Item itm = a.items[it];
+                if ((int)itm.inst != sc_loaded) {
+                    if (threadIdx.x < NV) {
+                        const int p = itm.inst * NV + threadIdx.x;
+                        sc_a[threadIdx.x] = a.alpha[(size_t)p * a.steps + k] *
+                                            a.sigma[(size_t)p * (a.steps + 1) + k];
+                    }
+                    if (threadIdx.x == 0) {
+                        const InstDesc &d = a.inst[itm.inst];
+                        sb_dim = d.dim;
+                        sb_vec_off = d.vec_off;
+                        sb_item_end = d.item_first + d.item_count;
+                    }
+                    sc_loaded = itm.inst;
+                    __syncthreads();
                 }
-                store_row<NV>(w + row, wv);
+                const uint32_t dim = __builtin_amdgcn_readfirstlane(sb_dim);
+                const uint32_t vec_off = __builtin_amdgcn_readfirstlane(sb_vec_off);
+                const uint32_t item_end = __builtin_amdgcn_readfirstlane(sb_item_end);
+                const uint32_t i = itm.row0 + threadIdx.x;
+                if (i < dim) {
+                    const size_t row = ((size_t)vec_off + i) * NV;
+                    float wv[NV], rv[NV];
+                    load_row<NV>(w + row, wv);
+                    load_row<NV>(rk + row, rv);
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        wv[q] = (float)((double)wv[q] - sc_a[q] * (double)rv[q]);
+                        ss[q] += (double)wv[q] * (double)wv[q];
+                    }
+                    store_row<NV>(w + row, wv);
+                }
+                if (it + 1 == i1 || (uint32_t)(it + 1) == item_end) {
+                    item_partials<NV>(ss, stage, a.partial + (size_t)seg * NV);
+    #pragma unroll
+                    for (int q = 0; q < NV; ++q) ss[q] = 0.0;
+                    seg = it + 1;
+                }
             }
-            item_partials<NV>(ss, stage, a.partial + (size_t)it * NV);
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- B': beta, breakdown, next sigma / cprev -----------------------
@@ -507,7 +606,7 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
     std::vector<hm::InstDesc> desc(ninst);
     std::vector<hm::Item> items;
     uint32_t vec_off = 0;
-    int max_prefix = 0;
+    int max_prefix = 0, max_bonds = 0;
     for (int k = 0; k < ninst; ++k) {
         hm::Basis *b = &bases[k]->impl;
         if (!d_v0[k]) return fail(HM_EINVAL, "start vectors of instance %d are null", k);
@@ -529,6 +628,7 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
         d.v0 = d_v0[k];
         vec_off += d.dim;
         max_prefix = std::max(max_prefix, (int)b->prefix_len());
+        max_bonds = std::max(max_bonds, c->nb);
     }
     HM_HIP(hipMemcpyAsync(w + L.desc, desc.data(), sizeof(hm::InstDesc) * ninst,
                           hipMemcpyHostToDevice, st));
@@ -557,8 +657,10 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
     a.norm0 = (double *)(w + L.norm0);
     a.stopped = (int *)(w + L.stopped);
     a.max_prefix = max_prefix;
+    a.max_bonds = max_bonds;
     const size_t lds = ((size_t)(max_prefix * 4 + 15) / 16) * 16 + 32 * sizeof(double) +
-                       (size_t)hm::kBatchBlock * L.NV * sizeof(double);
+                       (size_t)hm::kStageWaves * L.NV * sizeof(double) +
+                       (size_t)max_bonds * sizeof(hm::LdsBond);
     const int bits = bases[0]->impl.bits;
     int grid = 0, rc;
     switch (L.NV) {
