@@ -133,18 +133,23 @@ def extras():
         row_vector_steps_per_s=prob.rows * 16 * 80 / dt,
         E0_spread_max=float(np.max(np.ptp(r.E0, axis=1))))
     # magnetization curve of the N=24 J1-J2 ring: 13 sectors M >= 0, 2 start
-    # vectors each, 150 steps, one launch; then finite-temperature Lanczos of
-    # the N=20 ring, 11 sectors x 16 vectors x 60 steps
+    # vectors each, 150 steps (one Lanczos run per sector and vector on the
+    # block kernel, and the batched path for comparison); then finite-
+    # temperature Lanczos of the N=20 ring, 11 sectors x 16 vectors x 60 steps
     from paper_0706_3293_amd import ftl_thermodynamics, magnetization_curve
     J24 = inputs.ring_couplings(24, -1.0, -0.25)
-    magnetization_curve(24, 1, J24, 150, nvec=2, seed=0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    c = magnetization_curve(24, 1, J24, 150, nvec=2, seed=0)
-    dt = time.perf_counter() - t0
+    curve = {}
+    for method in ("single", "batched"):
+        magnetization_curve(24, 1, J24, 150, nvec=2, seed=0, method=method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = magnetization_curve(24, 1, J24, 150, nvec=2, seed=0, method=method)
+        curve[method] = (1e3 * (time.perf_counter() - t0), c)
+    c = curve["single"][1]
     out["magnetization_curve_ring24"] = dict(
-        ms=1e3 * dt, sectors=len(c.two_M), rows=int(c.dim.sum()), vectors=2, steps=150,
-        E0=[float(e) for e in c.E0])
+        ms=curve["single"][0], ms_batched_path=curve["batched"][0], sectors=len(c.two_M),
+        rows=int(c.dim.sum()), vectors=2, steps=150, E0=[float(e) for e in c.E0],
+        max_abs_diff_paths=float(np.abs(c.E0 - curve["batched"][1].E0).max()))
     J20 = inputs.ring_couplings(20, -1.0, -0.25)
     temps = [0.1, 0.25, 0.5, 1.0, 2.0, 4.0]
     ftl_thermodynamics(20, 1, J20, temps, 60, nvec=16, seed=0)

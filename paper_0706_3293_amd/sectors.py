@@ -73,15 +73,38 @@ def _run(N, two_s, J, steps, nvec, seed, V0s, tol):
 
 
 def magnetization_curve(N: int, two_s: int, J, steps: int, nvec: int = 1, seed: int = 0,
-                        V0s=None, tol: float = 0.0) -> MagnetizationCurve:
-    """E0 of every sector M >= 0 in one batched launch (FP32 vectors, FP64
-    coefficients).  V0s: optional list of (nvec, dim) start vectors per sector
-    in the order of sector_two_M."""
-    bases, res = _run(N, two_s, J, steps, nvec, seed, V0s, tol)
+                        V0s=None, tol: float = 0.0, method: str = "auto") -> MagnetizationCurve:
+    """E0 of every sector M >= 0 (FP32 vectors, FP64 coefficients and sums).
+
+    method "batched": all sectors and start vectors in one persistent launch
+    (hm_lanczos_batched); "single": one hm_lanczos run per sector and start
+    vector, which for s = 1/2 runs the block H x kernel; "auto": single for
+    s = 1/2, batched otherwise.  V0s: optional list of (nvec, dim) start
+    vectors per sector in the order of sector_two_M."""
+    if method == "auto":
+        method = "single" if two_s == 1 else "batched"
+    if method == "batched":
+        bases, res = _run(N, two_s, J, steps, nvec, seed, V0s, tol)
+        E0_runs, done = res.E0, res.steps_done
+    elif method == "single":
+        bases = sector_bases(N, two_s)
+        if V0s is None:
+            V0s = random_start_vectors(bases, nvec, seed)
+        E0_runs = np.zeros((len(bases), nvec))
+        done = np.zeros((len(bases), nvec), dtype=np.int32)
+        for k, (b, V) in enumerate(zip(bases, V0s)):
+            V = V if torch.is_tensor(V) else torch.as_tensor(np.asarray(V))
+            V = V.to("cuda", torch.float64)
+            for r in range(nvec):
+                res = b.lanczos(J, V[r].contiguous(), steps, precision="f32_mixed", tol=tol)
+                E0_runs[k, r] = res.E0
+                done[k, r] = res.steps_done
+    else:
+        raise ValueError(f"unknown method {method!r}")
     return MagnetizationCurve(
         two_M=np.array(sector_two_M(N, two_s)),
         dim=np.array([b.dim for b in bases], dtype=np.int64),
-        E0=res.E0.min(axis=1), E0_runs=res.E0, steps_done=res.steps_done)
+        E0=E0_runs.min(axis=1), E0_runs=E0_runs, steps_done=done)
 
 
 def thermo_sums(levels, weights, temps):

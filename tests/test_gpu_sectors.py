@@ -22,13 +22,15 @@ def _random_chain(N, seed):
     return J
 
 
-@pytest.mark.parametrize("N,two_s,kind", [(12, 1, "ring"), (8, 2, "chain"), (5, 3, "chain")])
-def test_magnetization_curve_matches_oracle(N, two_s, kind):
+@pytest.mark.parametrize("N,two_s,kind,method", [
+    (12, 1, "ring", "batched"), (12, 1, "ring", "single"), (8, 2, "chain", "auto"),
+    (5, 3, "chain", "auto"), (6, 2, "chain", "single")])
+def test_magnetization_curve_matches_oracle(N, two_s, kind, method):
     from oracle import sectors as osec
     from paper_0706_3293_amd import inputs, magnetization_curve
-    print("magnetization curve", N, two_s, kind, flush=True)
+    print("magnetization curve", N, two_s, kind, method, flush=True)
     J = inputs.ring_couplings(N, -1.0, -0.3) if kind == "ring" else _random_chain(N, N)
-    curve = magnetization_curve(N, two_s, J, steps=150, nvec=2, seed=1)
+    curve = magnetization_curve(N, two_s, J, steps=150, nvec=2, seed=1, method=method)
     want = osec.sector_energies(N, two_s, J)
     assert list(curve.two_M) == [N * two_s - 2 * A for A in osec.sector_lowerings(N, two_s)]
     s = two_s / 2
