@@ -159,6 +159,30 @@ def extras():
     dt = time.perf_counter() - t0
     out["ftl_ring20"] = dict(ms=1e3 * dt, sectors=11, vectors=16, steps=60, T=temps,
                              E=[float(e) for e in th["E"]], C=[float(x) for x in th["C"]])
+    # the paper's design alternatives for H x, FP32, ms per apply: 1 generic
+    # row gather (decode every row), 2 spin-1/2 block kernel, 3 successor
+    # sweep (decode one row in 16), 4 column scatter with atomic adds
+    abl = {}
+    cases = (("s1/2 N=28 J1-J2 ring M=0", 28, 1, inputs.ring_couplings(28, -1.0, -0.5), (1, 2, 3, 4)),
+             ("s1 N=16 chain M=0", 16, 2, inputs.chain_couplings(-np.ones(15)), (1, 3, 4)))
+    for name, N, two_s, Jc, kernels in cases:
+        b = Basis(N, two_s=two_s, two_M=0)
+        x = torch.rand(b.dim, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        t = {"dim": b.dim}
+        for k in kernels:
+            b.apply(Jc, x, out=y, kernel=k)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                b.apply(Jc, x, out=y, kernel=k)
+            e1.record()
+            torch.cuda.synchronize()
+            t[f"kernel{k}_ms"] = e0.elapsed_time(e1) / 5
+        abl[name] = t
+        del x, y
+    out["hx_design_ablations"] = abl
     return out
 
 

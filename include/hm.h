@@ -147,8 +147,17 @@ int hm_apply(hm_basis h, const double *J, const void *d_x, void *d_y,
 
 /* hm_apply with an explicit choice of H x kernel: 1 = the generic digit
  * kernel (any s), 2 = the spin-1/2 block kernel (s = 1/2 only; HM_EINVAL
- * otherwise).  Both give y = H x; this entry point exists to cross-check them
- * and to time them separately. */
+ * otherwise).  Two more exist only to measure the paper's design
+ * alternatives (bits per digit <= 4):
+ *   3 = successor sweep (Sec. 3.1): each lane decodes the first of 16
+ *       consecutive rows and reaches the others with the successor
+ *       operation; y is bitwise equal to kernel 1's;
+ *   4 = column scatter (Sec. 4, the loop order the paper rejects for its
+ *       write conflicts): source row j outer, y_i += H_ij x_j with
+ *       floating-point atomic adds after y is cleared; the order of the
+ *       additions into each y_i varies from run to run.
+ * All give y = H x; this entry point exists to cross-check the kernels and
+ * to time them separately. */
 int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y,
                     int32_t dtype, int32_t kernel, void *stream);
 

@@ -58,7 +58,8 @@ int hm_apply(hm_basis h, const double *J, const void *d_x, void *d_y, int32_t dt
 }
 
 // Variant of hm_apply that forces one H x kernel (1: generic digits, 2: the
-// spin-1/2 block kernel); used to cross-check the two kernels.
+// spin-1/2 block kernel, 3: successor sweep, 4: column scatter); used to
+// cross-check the kernels and to time the paper's design alternatives.
 int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y, int32_t dtype,
                     int32_t kernel, void *stream) {
     hm::clear_error();
@@ -66,9 +67,10 @@ int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y, int
     if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_EINVAL, "unknown dtype %d", dtype);
     if (d_x == d_y) return fail(HM_EINVAL, "x and y must not alias");
     hm::Basis *b = &h->impl;
-    if (kernel < 1 || kernel > 2) return fail(HM_EINVAL, "kernel must be 1 or 2");
+    if (kernel < 1 || kernel > 4) return fail(HM_EINVAL, "kernel must be 1, 2, 3 or 4");
     const hm::Couplings *c = nullptr;
     HM_TRY(hm::get_couplings(b, J, &c));
+    if (kernel >= 3) return hm::launch_hx_ablation(b, c, dtype, kernel, d_x, d_y, (hipStream_t)stream);
     const int k = hm::choose_kernel(b, c, kernel);
     if (k < 0) return fail(HM_EINVAL, "kernel %d not applicable", kernel);
     hm::HxPass p;

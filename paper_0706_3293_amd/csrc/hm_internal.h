@@ -139,6 +139,9 @@ int hx_partial_count(const Basis *b, int kernel);      // partial slots needed
 int launch_hx(const Basis *b, const Couplings *c, int dtype, int kernel,
               const HxPass &pass, hipStream_t st);
 int choose_kernel(const Basis *b, const Couplings *c, int requested);
+// Ablation kernels of hm_apply_kernel: 3 = successor sweep, 4 = column scatter.
+int launch_hx_ablation(const Basis *b, const Couplings *c, int dtype, int kernel,
+                       const void *x, void *y, hipStream_t st);
 
 // Bond correlations.
 int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb,

@@ -9,10 +9,9 @@
 // bond list is read with wave-uniform (scalar) loads.
 #include "device_common.h"
 #include "hm_internal.h"
+#include "hx_row.h"
 
 namespace hm {
-
-constexpr size_t kMaxPrefixLds = 60 * 1024;
 
 template <typename T, typename I, int B, bool DOT, bool STORE>
 __global__ __launch_bounds__(kBlock) void hx_generic_kernel(
@@ -41,22 +40,7 @@ __global__ __launch_bounds__(kBlock) void hx_generic_kernel(
     for (I row = first + threadIdx.x; row < last; row += blockDim.x) {
         const uint64_t st = unrank_state<I, B>(row, pv, N, A, two_s);
         const T xi = x[row];
-        T diag = 0, off = 0;
-        for (int b = 0; b < nb; ++b) {
-            const int u = bonds[b].u, v = bonds[b].v;
-            const T mJ4 = (T)bonds[b].mJ4, mJ2 = (T)bonds[b].mJ2;
-            const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
-            diag += mJ4 * (T)((two_s - 2 * au) * (two_s - 2 * av));
-            if (au >= 1 && av < two_s) {   // s+(u) s-(v): a_u - 1, a_v + 1
-                const I j = row + move_delta<I, B>(st, u, v, -1, pv);
-                off += (mJ2 * F[au] * F[av + 1]) * x[j];
-            }
-            if (av >= 1 && au < two_s) {   // s-(u) s+(v): a_u + 1, a_v - 1
-                const I j = row + move_delta<I, B>(st, u, v, +1, pv);
-                off += (mJ2 * F[av] * F[au + 1]) * x[j];
-            }
-        }
-        const T hv = diag * xi + off;
+        const T hv = row_hx<T, I, B>(st, row, xi, x, bonds, nb, two_s, pv, F);
         double w = sigma * (double)hv;
         if (prev) w -= cprev * (double)prev[row];
         const T wt = (T)w;
@@ -117,18 +101,18 @@ __global__ __launch_bounds__(kBlock) void rank_kernel(const I *__restrict__ gpre
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static size_t prefix_bytes(const Basis *b) {
+size_t prefix_bytes(const Basis *b) {
     return b->prefix_len() * (b->idx32 ? sizeof(uint32_t) : sizeof(uint64_t));
 }
 
-static int check_lds(const Basis *b) {
+int check_lds(const Basis *b) {
     if (prefix_bytes(b) + 16 + (b->two_s + 2) * sizeof(double) > kMaxPrefixLds)
         return fail(HM_ERANGE, "prefix table (%zu bytes) exceeds the LDS budget",
                     prefix_bytes(b));
     return HM_OK;
 }
 
-static int grid_for(int64_t rows) {
+int generic_grid(int64_t rows) {
     int64_t g = (rows + kBlock - 1) / kBlock;
     if (g > kMaxGrid) g = kMaxGrid;
     if (g < 1) g = 1;
@@ -136,7 +120,7 @@ static int grid_for(int64_t rows) {
     return (int)g;
 }
 
-int hx_generic_grid(const Basis *b) { return grid_for(b->dim); }
+int hx_generic_grid(const Basis *b) { return generic_grid(b->dim); }
 
 template <typename T, typename I, int B>
 static void launch_hx_t(const Basis *b, const Couplings *c, const HxPass &p, int grid,
@@ -178,7 +162,7 @@ static int dispatch_bits(const Basis *b, const Couplings *c, const HxPass &p, in
 int launch_hx_generic(const Basis *b, const Couplings *c, int dtype, const HxPass &p,
                       hipStream_t st) {
     HM_TRY(check_lds(b));
-    const int grid = grid_for(b->dim);
+    const int grid = generic_grid(b->dim);
     const size_t lds = ((prefix_bytes(b) + 15) / 16) * 16 + (b->two_s + 2) * sizeof(double);
     int rc;
     if (dtype == HM_F64)
