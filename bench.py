@@ -183,6 +183,17 @@ def extras():
         abl[name] = t
         del x, y
     out["hx_design_ablations"] = abl
+    # block Lanczos: the 4 lowest levels of the N=24 J1-J2 ring at M=0 (dim
+    # 2,704,156), p = 4, 60 block steps with full reorthogonalization, FP64
+    b = Basis(24, two_s=1, two_M=0)
+    J24 = inputs.ring_couplings(24, -1.0, -0.25)
+    b.lowest_levels(J24, 4, steps=4, p=4, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lev = b.lowest_levels(J24, 4, steps=60, p=4, seed=0)
+    dt = time.perf_counter() - t0
+    out["block_lanczos_ring24"] = dict(ms=1e3 * dt, dim=b.dim, p=4, steps=60,
+                                       levels=[float(e) for e in lev])
     return out
 
 

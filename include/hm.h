@@ -219,6 +219,29 @@ int hm_lanczos_ritz(hm_basis h, const double *J, const double *d_v0,
 int hm_tridiag_lowest(int32_t k, const double *alpha, const double *beta,
                       double *eval, double *evec);
 
+/* ---------------------------------------------------------------------------
+ * Block Lanczos: several lowest eigenpairs of H on H(M) at once, degenerate
+ * ones included (the block form of the method's Lanczos recurrence, with p x p
+ * blocks in place of alpha_k and beta_k; FP64 throughout):
+ *   V_0 R_0 = X0;  W = H V_k - V_{k-1} B_{k-1}^T;  A_k = V_k^T W;
+ *   W -= V_k A_k;  twice W -= sum_{j<=k} V_j (V_j^T W);  V_{k+1} B_k = W
+ * (QR by Cholesky QR applied twice, B_k upper triangular).  The eigenvalues of
+ * the block tridiagonal matrix with diagonal blocks A_0..A_{n-1} and
+ * sub-diagonal blocks B_0..B_{n-2} (n = *steps_done) approximate the lowest
+ * eigenvalues.  p: 1, 2, 4, 8 or 16 (and <= dim); bits per digit <= 4.
+ * d_X0: device FP64 start block, row-interleaved [dim][p] (entry (i, q) at
+ * i * p + q), linearly independent columns (else HM_EINVAL).  d_work:
+ * hm_block_lanczos_workspace bytes of device memory, which hold all
+ * (steps + 1) blocks of the Krylov basis.  A, B: host arrays of steps * p * p
+ * doubles, row-major p x p blocks; unused entries are zero.  The run stops
+ * early when the block Krylov space is exhausted (the rest of W is at the
+ * rounding level of the recurrence).  Synchronizes `stream`.
+ * ------------------------------------------------------------------------- */
+int hm_block_lanczos_workspace(hm_basis h, int32_t p, int32_t steps, size_t *bytes);
+int hm_block_lanczos(hm_basis h, const double *J, const double *d_X0, int32_t p,
+                     int32_t steps, void *d_work, size_t work_bytes, double *A,
+                     double *B, int32_t *steps_done, void *stream);
+
 /* All Ritz values of a Lanczos tridiagonal and their Gauss weights (the
  * tridiagonal eigensolve of the method's final step, here with every
  * eigenpair).  values[j] (ascending) are the eigenvalues of the k x k matrix

@@ -7,7 +7,7 @@ successor and row-gather product live in oracle/oracle.c, written from Secs. 3
 and 4 of the paper; the Lanczos recurrence, the tridiagonal eigensolve
 (scipy), the stored-basis Ritz vector and the bond correlations live in
 oracle/lanczos.py; magnetization sectors and thermodynamic sums live in
-oracle/sectors.py; oracle/brute.py holds independent brute-force references
+oracle/sectors.py, the block recurrence in oracle/block.py; oracle/brute.py holds independent brute-force references
 used to pin the oracle.
 
 Parity status of each function (what pins it, see tests/test_oracle_*.py):
@@ -24,6 +24,9 @@ Parity status of each function (what pins it, see tests/test_oracle_*.py):
   exact_thermodynamics  pinned: two-site closed form, full Kronecker spectrum
   ftl_thermodynamics pinned: exact with canonical start vectors, T -> infinity
                      sum rule, T -> 0 limit
+  block_lanczos      pinned: p = 1 equals the scalar recurrence, lowest levels
+                     (degenerate pairs included) equal the dense spectrum,
+                     V^T V = I and V^T H V = T, full spectrum when exhausted
 """
 from .core import Subspace, count, count_table, max_threads  # noqa: F401
 from .lanczos import (bond_correlations, ground_state, lanczos,  # noqa: F401

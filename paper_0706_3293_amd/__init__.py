@@ -10,8 +10,8 @@ include/hm.h); this package is its thin Python binding:
   magnetization_curve, ftl_thermodynamics
                    E0(M) over all sectors and finite-temperature Lanczos sums
 """
-from .api import (Basis, LanczosResult, count, last_timing, set_timing,  # noqa: F401
-                  tridiag_lowest, tridiag_ritz)
+from .api import (Basis, LanczosResult, block_tridiag_eigenvalues, count,  # noqa: F401
+                  last_timing, set_timing, tridiag_lowest, tridiag_ritz)
 from .autograd import GroundStateEnergy, ground_state, ground_state_energy  # noqa: F401,E402
 from .batched import BatchedProblem, BatchedResult, lanczos_batched  # noqa: F401,E402
 from .sectors import (MagnetizationCurve, ftl_thermodynamics,  # noqa: F401,E402

@@ -195,6 +195,42 @@ class Basis:
                                     _stream()))
         return psi, alpha, beta
 
+    def block_lanczos(self, J, X0: torch.Tensor, steps: int):
+        """Block Lanczos from the p columns of X0 (device FP64, (dim, p) or
+        (p, dim)); returns the diagonal blocks A (n x p x p), the sub-diagonal
+        blocks B (n-1 x p x p) and n = the block steps done."""
+        assert X0.is_cuda and X0.dtype == torch.float64 and X0.dim() == 2
+        if X0.shape[0] != self.dim:
+            X0 = X0.T
+        p = int(X0.shape[1])
+        X0 = X0.contiguous()                     # row-interleaved [dim][p]
+        n = ctypes.c_size_t()
+        check(lib().hm_block_lanczos_workspace(self._h, p, steps, ctypes.byref(n)))
+        work = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        A = np.zeros((steps, p, p))
+        B = np.zeros((steps, p, p))
+        done = ctypes.c_int32()
+        Jh, Jp = self._J(J)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().hm_block_lanczos(self._h, Jp, _dptr(X0), p, steps, _dptr(work), work.numel(),
+                                     A.ctypes.data_as(dp), B.ctypes.data_as(dp),
+                                     ctypes.byref(done), _stream()))
+        k = done.value
+        return A[:k].copy(), B[: max(k - 1, 0)].copy(), k
+
+    def lowest_levels(self, J, count: int, steps: int, p: int = 4, seed: int = 0,
+                      X0: torch.Tensor = None) -> np.ndarray:
+        """The `count` lowest eigenvalues (with multiplicity, up to p-fold) from a
+        block Lanczos run: eigenvalues of the block tridiagonal matrix (host
+        FP64 dense eigensolve, the block form of the final tridiagonal step)."""
+        if X0 is None:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(int(seed))
+            X0 = torch.rand((self.dim, p), generator=g, dtype=torch.float64,
+                            device="cuda").mul_(2.0).sub_(1.0)
+        A, B, k = self.block_lanczos(J, X0, steps)
+        return block_tridiag_eigenvalues(A, B)[:count]
+
     def bond_corr(self, bonds, psi: torch.Tensor) -> np.ndarray:
         uv = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
         out = np.zeros(uv.shape[0])
@@ -228,6 +264,21 @@ def tridiag_ritz(alpha, beta):
     dp = ctypes.POINTER(ctypes.c_double)
     check(lib().hm_tridiag_ritz(k, ap, bp, vals.ctypes.data_as(dp), wts.ctypes.data_as(dp)))
     return vals, wts
+
+
+def block_tridiag_eigenvalues(A, B) -> np.ndarray:
+    """Eigenvalues (ascending) of the symmetric block tridiagonal matrix with
+    diagonal blocks A[k] and sub-diagonal blocks B[k] (block k+1, k)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    n, p = A.shape[0], A.shape[1]
+    T = np.zeros((n * p, n * p))
+    for k in range(n):
+        T[k * p:(k + 1) * p, k * p:(k + 1) * p] = A[k]
+        if k + 1 < n:
+            T[(k + 1) * p:(k + 2) * p, k * p:(k + 1) * p] = B[k]
+            T[k * p:(k + 1) * p, (k + 1) * p:(k + 2) * p] = B[k].T
+    return np.linalg.eigvalsh(T)
 
 
 def set_timing(enable: bool):
