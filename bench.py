@@ -194,6 +194,28 @@ def extras():
     dt = time.perf_counter() - t0
     out["block_lanczos_ring24"] = dict(ms=1e3 * dt, dim=b.dim, p=4, steps=60,
                                        levels=[float(e) for e in lev])
+    # the largest size: N=36 J1-J2 ring at M=0 (dim 9,075,135,300 > 2^32, 64-bit
+    # indices), one FP32 H x on the block kernel, 36 GB per vector
+    b = Basis(36, two_s=1, two_M=0)
+    J36 = inputs.ring_couplings(36, -1.0, -0.25)
+    x = torch.empty(b.dim, dtype=torch.float32, device="cuda")
+    for s0 in range(0, b.dim, 1 << 28):        # any values; filled chunk by chunk
+        x[s0:s0 + (1 << 28)].uniform_(-1.0, 1.0)
+    y = torch.empty_like(x)
+    b.apply(J36, x, out=y, kernel=2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        b.apply(J36, x, out=y, kernel=2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    # algorithmic bytes of a plain H x: read x once, write y once (8 B per row)
+    out["hx_ring36_f32"] = dict(ms=ms, dim=b.dim, rows_per_s=b.dim / (ms * 1e-3),
+                                alg_gbs=8 * b.dim / (ms * 1e-3) / 1e9)
+    del x, y
+    torch.cuda.empty_cache()
     return out
 
 

@@ -42,6 +42,9 @@ def bind(path: str):
                                   _i64p, _dblp, _dblp, _i64p, ctypes.c_int64,
                                   _dblp]
     lib.or_apply_rows.restype = ctypes.c_int
+    lib.or_apply_rows_hashed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         _i64p, _dblp, _i64p, ctypes.c_int64, _dblp]
+    lib.or_apply_rows_hashed.restype = ctypes.c_int
     lib.or_max_threads.argtypes = []
     lib.or_max_threads.restype = ctypes.c_int
     return lib
@@ -140,6 +143,21 @@ class Subspace:
             raise RuntimeError("oracle apply failed")
         return y
 
+    def apply_rows_hashed(self, J, rows) -> np.ndarray:
+        """(H x)_i for the listed rows, with x_j = hashed_input(j) (no x array:
+        checks rows of problems whose vectors do not fit in host memory)."""
+        J = self._J(J)
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        y = np.empty(rows.shape[0], dtype=np.float64)
+        rc = self._lib.or_apply_rows_hashed(self.N, self.two_s, self.A,
+                                            _ptr(self.D, ctypes.c_int64),
+                                            _ptr(J, ctypes.c_double),
+                                            _ptr(rows, ctypes.c_int64), rows.shape[0],
+                                            _ptr(y, ctypes.c_double))
+        if rc != 0:
+            raise RuntimeError("oracle apply_rows_hashed failed (row out of range?)")
+        return y
+
     def apply_rows(self, J, x, rows) -> np.ndarray:
         """(H x)_i for the listed rows i only."""
         J = self._J(J)
@@ -154,3 +172,12 @@ class Subspace:
         if rc != 0:
             raise RuntimeError("oracle apply_rows failed (row out of range?)")
         return y
+
+
+def hashed_input(idx) -> np.ndarray:
+    """The counter-based input of apply_rows_hashed: x_j = (top 24 bits of
+    j * 0x9E3779B97F4A7C15 mod 2^64) / 2^24 - 1/2 (Knuth's multiplicative
+    hash), exact in FP32 and FP64."""
+    j = np.asarray(idx, dtype=np.uint64)
+    h = j * np.uint64(0x9E3779B97F4A7C15)
+    return (h >> np.uint64(40)).astype(np.float64) / 16777216.0 - 0.5

@@ -191,6 +191,19 @@ OR_EXPORT int or_successor(int N, int two_s, int *a)
  * read.  `cur` is the digit string of row i and is left unchanged; `work`
  * must hold N ints.
  * ------------------------------------------------------------------------- */
+/* x_j of the input vector: x[j], or, when x is NULL, the counter-based value
+ * of index j (Knuth's multiplicative hash with the 64-bit golden-ratio
+ * constant, top 24 bits as a fraction, minus 1/2; exact in FP32 and FP64).
+ * The hashed form checks single rows of problems whose vectors do not fit in
+ * host memory. */
+static double x_at(const double *x, int64_t j)
+{
+    if (x)
+        return x[j];
+    const uint64_t h = (uint64_t)j * 0x9E3779B97F4A7C15ull;
+    return (double)(h >> 40) / 16777216.0 - 0.5;
+}
+
 static double apply_row(int N, int two_s, int A, const int64_t *D,
                         const double *J, const double *x, int64_t i,
                         const int *cur, int *work)
@@ -213,7 +226,7 @@ static double apply_row(int N, int two_s, int A, const int64_t *D,
                 work[u] -= 1;
                 work[v] += 1;
                 int64_t j = or_rank(N, two_s, A, D, work);
-                y += -0.5 * Juv * f * x[j];
+                y += -0.5 * Juv * f * x_at(x, j);
             }
             /* s-(u) s+(v) */
             if (cur[v] >= 1 && cur[u] <= two_s - 1) {
@@ -223,11 +236,11 @@ static double apply_row(int N, int two_s, int A, const int64_t *D,
                 work[v] -= 1;
                 work[u] += 1;
                 int64_t j = or_rank(N, two_s, A, D, work);
-                y += -0.5 * Juv * f * x[j];
+                y += -0.5 * Juv * f * x_at(x, j);
             }
         }
     }
-    return diag * x[i] + y;
+    return diag * x_at(x, i) + y;
 }
 
 /* ---------------------------------------------------------------------------
@@ -294,6 +307,14 @@ OR_EXPORT int or_apply_rows(int N, int two_s, int A, const int64_t *D,
         free(work);
     }
     return failed ? -1 : 0;
+}
+
+/* or_apply_rows with the counter-based input x_j of x_at (no x array). */
+OR_EXPORT int or_apply_rows_hashed(int N, int two_s, int A, const int64_t *D,
+                                   const double *J, const int64_t *rows, int64_t nrows,
+                                   double *y)
+{
+    return or_apply_rows(N, two_s, A, D, J, NULL, rows, nrows, y);
 }
 
 /* Number of threads the OpenMP runtime would use (1 without OpenMP). */

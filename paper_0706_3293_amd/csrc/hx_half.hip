@@ -40,7 +40,7 @@ constexpr int kHalfMaxK = 14;
 constexpr int kHalfMaxHighBits = 24;
 constexpr int kGroup = 8;
 constexpr uint32_t kNoHigh = 0xFFFFFFFFu;      // padding slot of a high-word group
-constexpr size_t kMaxNeighbourBytes = (size_t)1 << 30;
+constexpr size_t kMaxNeighbourBytes = (size_t)4 << 30;
 
 // Eight bonds of one group, structure-of-arrays so one group is fetched with
 // a few wide scalar loads.

@@ -66,6 +66,20 @@ def test_apply_rows_matches_apply():
     assert np.array_equal(sub.apply_rows(J, x, rows), y[rows])
 
 
+def test_hashed_input_rows_match_apply():
+    # the counter-based input: its values are exact multiples of 2^-24 in
+    # [-1/2, 1/2), and rows computed from it equal H x with x materialized
+    from oracle.core import hashed_input
+    sub = oracle.Subspace(14, 2, 14)
+    J = inputs.chain_couplings(np.linspace(-1.0, -0.5, 13))
+    x = hashed_input(np.arange(sub.dim))
+    assert x.min() >= -0.5 and x.max() < 0.5
+    assert np.all(x * 2 ** 24 == np.round(x * 2 ** 24))
+    assert hashed_input([0, 1])[0] == -0.5 and abs(hashed_input([1])[0] - 0.1180338) < 1e-6
+    rows = np.random.default_rng(3).integers(0, sub.dim, 300)
+    assert np.array_equal(sub.apply_rows_hashed(J, rows), sub.apply(J, x)[rows])
+
+
 def test_dimer_closed_form():
     """Two spins: H = -J s1.s2 has E = -(J/2)[S(S+1) - 2 s(s+1)]."""
     for two_s in (1, 2, 3, 4):

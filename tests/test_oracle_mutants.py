@@ -18,8 +18,8 @@ SRC = os.path.join(os.path.dirname(core.__file__), "oracle.c")
 
 MUTANTS = {
     "diagonal_sign": ("diag += -Juv * mu * mv;", "diag += Juv * mu * mv;"),
-    "dropped_half": ("y += -0.5 * Juv * f * x[j];\n            }\n            /* s-(u) s+(v) */",
-                     "y += -1.0 * Juv * f * x[j];\n            }\n            /* s-(u) s+(v) */"),
+    "dropped_half": ("y += -0.5 * Juv * f * x_at(x, j);\n            }\n            /* s-(u) s+(v) */",
+                     "y += -1.0 * Juv * f * x_at(x, j);\n            }\n            /* s-(u) s+(v) */"),
     "ladder_factor": ("sqrt((double)cur[u] * (two_s - cur[u] + 1)) *",
                       "sqrt((double)cur[u] * (two_s - cur[u])) *"),
     "rank_off_by_one": ("for (int n = 0; n < a[k - 1]; ++n)",
@@ -31,8 +31,8 @@ MUTANTS = {
                         "for (int k = 0; k < two_s; ++k) {\n                int prev"),
     "successor_refill": ("int put = balls < two_s ? balls : two_s;",
                          "int put = balls < two_s - 1 ? balls : (two_s > 1 ? two_s - 1 : 1);"),
-    "second_ladder_dropped": ("                y += -0.5 * Juv * f * x[j];\n            }\n        }\n    }",
-                              "                y += 0.0 * Juv * f * x[j];\n            }\n        }\n    }"),
+    "second_ladder_dropped": ("                y += -0.5 * Juv * f * x_at(x, j);\n            }\n        }\n    }",
+                              "                y += 0.0 * Juv * f * x_at(x, j);\n            }\n        }\n    }"),
     "swapped_sites": ("work[u] -= 1;\n                work[v] += 1;",
                       "work[u] += 1;\n                work[v] -= 1;"),
 }
