@@ -390,13 +390,22 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
     HM_HIP(hipGetLastError());
 
     const bool timing = g_timing;
+    // timing events, destroyed on every return path
+    struct Events {
+        std::vector<hipEvent_t> e;
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
     std::vector<hipEvent_t> ev;
     hipEvent_t lo = nullptr, hi = nullptr;
     if (timing) {
-        ev.resize(2 * (size_t)R.steps);
-        for (auto &e : ev) HM_HIP(hipEventCreate(&e));
-        HM_HIP(hipEventCreate(&lo));
-        HM_HIP(hipEventCreate(&hi));
+        evs.e.assign(2 * (size_t)R.steps + 2, nullptr);
+        for (auto &e : evs.e) HM_HIP(hipEventCreate(&e));
+        ev.assign(evs.e.begin(), evs.e.begin() + 2 * (size_t)R.steps);
+        lo = evs.e[2 * (size_t)R.steps];
+        hi = evs.e[2 * (size_t)R.steps + 1];
         HM_HIP(hipEventRecord(lo, R.st));
     }
     int rc = HM_OK;
@@ -453,9 +462,6 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
         g_hx_ms = hx;
         g_hx_launches = done;
         g_loop_ms = loop;
-        for (auto &e : ev) (void)hipEventDestroy(e);
-        (void)hipEventDestroy(lo);
-        (void)hipEventDestroy(hi);
     }
     return HM_OK;
 }
