@@ -86,6 +86,68 @@ def cpu_baseline(N, J, x, rows):
                        f"({dt:.1f} s on the host)")
 
 
+# The oracle timed in a child process (no GPU), so that OMP_NUM_THREADS can be
+# set per run: rows/s of its H x on a row sample of the main workload, a full
+# N=12 Lanczos run and one full N=20 all-to-all H x.
+_ORACLE_CHILD = r"""
+import json, sys, time
+import numpy as np
+cfg = json.load(sys.stdin)
+sys.path.insert(0, cfg["root"])
+import oracle
+out = {"threads": oracle.max_threads()}
+J = np.array(cfg["J"])
+sub = oracle.Subspace(cfg["N"], 1, cfg["N"] // 2)
+x = np.random.default_rng(0).uniform(-1.0, 1.0, sub.dim)
+rows = np.sort(np.random.default_rng(1).integers(0, sub.dim, cfg["rows"]))
+t0 = time.perf_counter(); sub.apply_rows(J, x, rows); dt = time.perf_counter() - t0
+out["hx_rows_per_s"] = cfg["rows"] / dt
+out["hx_sample_rows"] = cfg["rows"]
+if cfg["full_runs"]:
+    J12 = np.array(cfg["J12"]); s12 = oracle.Subspace(12, 1, 6)
+    v12 = np.random.default_rng(0).uniform(-1.0, 1.0, s12.dim)
+    t0 = time.perf_counter(); r = oracle.lanczos(s12, J12, v12, 120, full_reorth=True)
+    out["ring12_120_steps_s"] = time.perf_counter() - t0; out["ring12_E0"] = r["E0"]
+    J20 = np.array(cfg["J20"]); s20 = oracle.Subspace(20, 1, 10)
+    v20 = np.random.default_rng(0).uniform(-1.0, 1.0, s20.dim)
+    t0 = time.perf_counter(); s20.apply(J20, v20)
+    out["all_to_all20_hx_s"] = time.perf_counter() - t0
+print(json.dumps(out))
+"""
+
+
+def oracle_child(N, J, rows, threads, full_runs):
+    import subprocess
+    from paper_0706_3293_amd import inputs
+    cfg = dict(root=ROOT, N=N, J=np.asarray(J).tolist(), rows=rows, full_runs=full_runs,
+               J12=inputs.ring_couplings(12, -1.0).tolist(),
+               J20=inputs.all_to_all_couplings(20, 0)[0].tolist())
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    res = subprocess.run([sys.executable, "-c", _ORACLE_CHILD], input=json.dumps(cfg),
+                         capture_output=True, text=True, env=env, timeout=300)
+    if res.returncode != 0:
+        return {"error": res.stderr[-500:]}
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["mem_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -296,10 +358,14 @@ def main():
         other = extras()
         log(f"other workloads: {json.dumps(other)}")
 
-    cpu = None
+    cpu = cpu_detail = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, J, v0_host, args.cpu_rows)
         log(f"cpu baseline {cpu['value']:.3g} rows/s on {cpu['cores']} threads")
+        cpu_detail = {"host": host_info(),
+                      "one_thread": oracle_child(N, J, 1 << 18, 1, False),
+                      "all_threads": oracle_child(N, J, 1 << 22, 0, True)}
+        log(f"cpu baseline detail: {json.dumps(cpu_detail)}")
 
     mixed, f64 = results["f32_mixed"], results["f64"]
     ref = exact if exact is not None else f64["E0"]
@@ -337,6 +403,7 @@ def main():
                      "kernel": "hx_half_kernel<float, uint32, R, DOT=true>",
                      "alg_bytes_per_launch": h32["alg_bytes"]},
         "cpu_baseline": cpu,
+        "cpu_baseline_detail": cpu_detail,
         "other_workloads": other,
     }
     print(json.dumps(line), flush=True)
