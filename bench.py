@@ -112,6 +112,12 @@ if cfg["full_runs"]:
     v20 = np.random.default_rng(0).uniform(-1.0, 1.0, s20.dim)
     t0 = time.perf_counter(); s20.apply(J20, v20)
     out["all_to_all20_hx_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); sub.apply(J, x)
+    out["main_workload_full_hx_s"] = time.perf_counter() - t0
+    Jp = np.array(cfg["Jp"]); sp = oracle.Subspace(20, 2, 7)
+    vp = np.random.default_rng(0).uniform(-1.0, 1.0, sp.dim)
+    t0 = time.perf_counter(); oracle.lanczos(sp, Jp, vp, 10)
+    out["paper_vector_length_s_per_step"] = (time.perf_counter() - t0) / 10
 print(json.dumps(out))
 """
 
@@ -121,7 +127,8 @@ def oracle_child(N, J, rows, threads, full_runs):
     from paper_0706_3293_amd import inputs
     cfg = dict(root=ROOT, N=N, J=np.asarray(J).tolist(), rows=rows, full_runs=full_runs,
                J12=inputs.ring_couplings(12, -1.0).tolist(),
-               J20=inputs.all_to_all_couplings(20, 0)[0].tolist())
+               J20=inputs.all_to_all_couplings(20, 0)[0].tolist(),
+               Jp=inputs.ring_couplings(20, -1.0).tolist())
     env = dict(os.environ)
     if threads:
         env["OMP_NUM_THREADS"] = str(threads)
@@ -190,9 +197,13 @@ def extras():
     t0 = time.perf_counter()
     r = prob.run()
     dt = time.perf_counter() - t0
+    # compulsory bytes per (row, vector, step): pass A reads r_k and r_{k-1}
+    # and writes w, pass B reads w and r_k and writes w: 6 x 4 B in FP32
+    alg_gbs = prob.rows * 16 * 80 * 24 / dt / 1e9
     out["spin1_chains_batched"] = dict(
         ms=1e3 * dt, instances=64, vectors=16, steps=80, rows=prob.rows,
         row_vector_steps_per_s=prob.rows * 16 * 80 / dt,
+        alg_gbs=alg_gbs, hbm_frac=alg_gbs / HBM_PEAK_GBS,
         E0_spread_max=float(np.max(np.ptp(r.E0, axis=1))))
     # magnetization curve of the N=24 J1-J2 ring: 13 sectors M >= 0, 2 start
     # vectors each, 150 steps (one Lanczos run per sector and vector on the
@@ -256,6 +267,19 @@ def extras():
     dt = time.perf_counter() - t0
     out["block_lanczos_ring24"] = dict(ms=1e3 * dt, dim=b.dim, p=4, steps=60,
                                        levels=[float(e) for e in lev])
+    # the vector length of the paper's only timing experiment (200 Lanczos
+    # iterations, length 484,500 = D(N=20, s=1, M=13); the system is not
+    # named, so an N=20 spin-1 ring stands in), FP64
+    b = Basis(20, two_s=2, two_M=26)
+    Jp = inputs.ring_couplings(20, -1.0)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+    b.lanczos(Jp, v0, 200)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = b.lanczos(Jp, v0, 200)
+    dt = time.perf_counter() - t0
+    out["paper_vector_length_484500"] = dict(ms=1e3 * dt, dim=b.dim, steps=200,
+                                             ms_per_step=1e3 * dt / 200, E0=res.E0)
     # the largest size: N=36 J1-J2 ring at M=0 (dim 9,075,135,300 > 2^32, 64-bit
     # indices), one FP32 H x on the block kernel, 36 GB per vector
     b = Basis(36, two_s=1, two_M=0)
