@@ -186,7 +186,7 @@ def extras():
     E0.backward()
     t2 = time.perf_counter()
     out["all_to_all20"] = dict(forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1),
-                               steps=300, bonds=len(bonds), E0=float(E0),
+                               steps=300, bonds=len(bonds), E0=float(E0.detach()),
                                euler_residual=abs(float(np.dot(vals, Jv.grad.numpy())) - float(E0)))
     # 64 spin-1 chains x 16 start vectors x 80 steps, one persistent launch
     inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)

@@ -100,6 +100,29 @@ def test_block_kernel_full_size_sampled_rows(N):
     assert np.abs(got32 - ref32).max() <= 2e-6 * scale
 
 
+@pytest.mark.parametrize("precision,schedule", [("f32_mixed", (13, 256, 8)),
+                                                ("f64", (13, 256, 4))])
+def test_bench_configuration_lanczos_n28(precision, schedule):
+    """The timed workload in the launch configuration the benchmark uses (the
+    autotuner's schedules on MI355X): 200 steps reach the exact Majumdar-Ghosh
+    energy, and the first coefficients equal the oracle's."""
+    import oracle
+    from paper_0706_3293_amd import inputs
+    N = 28
+    print("bench configuration", precision, schedule, flush=True)
+    b = _basis(N, N // 2, *schedule)
+    J = inputs.ring_couplings(N, -1.0, -0.5)
+    v0h = inputs.start_vector(b.dim, 0)
+    v0 = torch.tensor(v0h, device="cuda")
+    res = b.lanczos(J, v0, 200, precision=precision)
+    tol = 1e-10 if precision == "f64" else 1e-7
+    assert abs(res.E0 + 3 * N / 8) <= tol * 3 * N / 8
+    ref = oracle.lanczos(oracle.Subspace(N, 1, N // 2), J, v0h, 2)
+    ctol = 1e-12 if precision == "f64" else 1e-6
+    assert np.abs(res.alpha[:2] - ref["alpha"]).max() <= ctol * np.abs(ref["alpha"]).max()
+    assert abs(res.beta[0] - ref["beta"][0]) <= ctol * ref["beta"][0]
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
 def test_block_kernel_lanczos_majumdar_ghosh(precision):
     from paper_0706_3293_amd import inputs
