@@ -37,14 +37,15 @@ class GroundStateEnergy(torch.autograd.Function):
         ctx.opts = dict(precision=precision, kernel=kernel, tol=tol)
         ctx.steps_done, ctx.c = res.steps_done, c
         ctx.lanczos = res
-        return torch.tensor(E0, dtype=torch.float64)
+        ctx.jdevice, ctx.jdtype = Jvals.device, Jvals.dtype
+        return torch.tensor(E0, dtype=torch.float64, device=Jvals.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         psi, alpha, beta = ctx.basis.ritz(ctx.J, ctx.v0, ctx.steps_done, ctx.c, **ctx.opts)
         corr = ctx.basis.bond_corr(ctx.bonds, psi)
         grad = -float(grad_out) * torch.tensor(corr, dtype=torch.float64)
-        return grad, None, None, None, None, None, None, None
+        return (grad.to(ctx.jdevice, ctx.jdtype), None, None, None, None, None, None, None)
 
 
 def ground_state_energy(Jvals, basis, bonds, v0, steps, precision="f64", kernel=0, tol=0.0):

@@ -124,3 +124,25 @@ def test_gradient_small_general_spin_vs_dense():
                       for u, v in bonds])
     assert abs(float(E0) - w[0]) < 1e-10
     assert np.abs(Jv.grad.numpy() - dense).max() < 1e-8
+
+
+def test_gradient_of_device_and_float32_couplings():
+    """Couplings held on the GPU (or in FP32) get E0 and the gradient on their
+    own device and dtype, equal to the FP64 host result."""
+    from paper_0706_3293_amd import Basis, ground_state_energy, inputs
+    N = 12
+    b = Basis(N, two_s=1, two_M=0)
+    _, bonds, vals = inputs.all_to_all_couplings(N, 4)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+    Jh = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+    ground_state_energy(Jh, b, bonds, v0, 120).backward()
+    Jd = torch.tensor(vals, dtype=torch.float64, device="cuda", requires_grad=True)
+    E0d = ground_state_energy(Jd, b, bonds, v0, 120)
+    E0d.backward()
+    assert E0d.device.type == "cuda" and Jd.grad.device.type == "cuda"
+    assert torch.equal(Jd.grad.cpu(), Jh.grad)
+    Jf = torch.tensor(vals, dtype=torch.float32, device="cuda", requires_grad=True)
+    ground_state_energy(Jf, b, bonds, v0, 120).backward()
+    assert Jf.grad.dtype == torch.float32
+    # the couplings themselves were rounded to FP32 here: same gradient to FP32 accuracy
+    assert (Jf.grad.double().cpu() - Jh.grad).abs().max() < 1e-5
