@@ -177,9 +177,14 @@ typedef struct hm_lanczos_opts {
     double breakdown_tol; /* relative; <= 0 selects 1e-12 (FP64) or 1e-6     *
                            * (FP32-mixed: the FP32 rounding floor of beta) */
     int32_t use_graph;    /* 1: capture all steps in one hipGraph           */
-    int32_t kernel;       /* 0: automatic choice of H x kernel; 1: generic
-                             digit kernel; 2: spin-1/2 block kernel (if the
-                             basis is spin 1/2)                              */
+    int32_t kernel;       /* 0: automatic choice (the one-workgroup run for
+                             dim <= 2048, else the H x kernel that suits
+                             the basis); 1: generic digit kernel; 2:
+                             spin-1/2 block kernel (if the basis is spin
+                             1/2); 3: one-workgroup run (every step in one
+                             launch of a single 1024-thread workgroup with
+                             the generic row product; dim <= 2^20, else
+                             HM_ERANGE; use_graph is ignored)            */
 } hm_lanczos_opts;
 
 /* Bytes of device workspace hm_lanczos / hm_lanczos_ritz need. */

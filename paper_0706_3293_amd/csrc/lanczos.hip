@@ -21,6 +21,7 @@
 
 #include "device_common.h"
 #include "hm_internal.h"
+#include "hx_row.h"
 
 namespace hm {
 
@@ -64,8 +65,13 @@ struct LzDev {
     double psi_norm;
 };
 
+// One-workgroup run (below): automatic choice up to kSmallAutoDim rows,
+// accepted when asked for explicitly up to kSmallMaxDim.
+constexpr int64_t kSmallAutoDim = 2048;
+constexpr int64_t kSmallMaxDim = 1 << 20;
+
 struct Layout {
-    size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, r0, r1, r2, V, total;
+    size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, r0, r1, r2, V, states, total;
     int grid_vec, nparts;
 };
 
@@ -102,6 +108,9 @@ static Layout layout(const Basis *b, int steps, int prec, int reorth) {
     L.r2 = off; off = align256(off + es * (size_t)b->dim);
     L.V = off;
     if (reorth) off = align256(off + es * (size_t)b->dim * (size_t)steps);
+    // decoded states of the one-workgroup run (any basis it may take)
+    L.states = off;
+    if (b->dim <= kSmallMaxDim) off = align256(off + sizeof(uint64_t) * (size_t)b->dim);
     L.total = off;
     return L;
 }
@@ -232,14 +241,16 @@ __global__ __launch_bounds__(kBlock) void reorth_dots(const T *__restrict__ V,
     if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void reorth_finish(const double *partial, int G, int nv,
-                                                        double *h, const LzDev *lz) {
+// h_j = sum of the G partials of coefficient j: one wave per j (blockIdx.x),
+// lanes over the partials, a fixed butterfly.
+__global__ __launch_bounds__(64) void reorth_finish(const double *partial, int G, double *h,
+                                                    const LzDev *lz) {
     if (lz->stopped) return;
-    __shared__ double red[16];
-    for (int j = 0; j < nv; ++j) {
-        const double s = fixed_sum(partial + (size_t)j * G, G, red);
-        if (threadIdx.x == 0) h[j] = s;
-    }
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < G; t += 64) s += partial[(size_t)j * G + t];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) h[j] = s;
 }
 
 template <typename T>
@@ -295,6 +306,168 @@ __global__ void zero_f64(double *__restrict__ x, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Small problems: the whole run in one workgroup.
+//
+// For a few thousand rows a step is little work, but the multi-kernel step
+// costs four launches (eleven with full reorthogonalization).  Here one
+// workgroup of 1024 threads runs every step in a single launch: thread t owns
+// rows t, t + 1024, ... (the generic row of hx_row.h, on states decoded once
+// at the start and kept in the workspace), reductions are fixed
+// trees (block_sum, wave_sum), and workgroup barriers order the passes, so a
+// run is reproducible and the recompute pass repeats it bit for bit.  The
+// recurrence is the same (Paige's ordering, the same breakdown test); v_k is
+// stored normalized.  One compute unit does all the row work, so the run pays
+// off only while that work stays below the launch costs it saves: measured,
+// up to about 2000 rows without reorthogonalization, and about 1000 rows with
+// it (where it takes a third of the multi-kernel time).
+// ---------------------------------------------------------------------------
+constexpr int kSmallBlock = 1024;
+
+template <typename T, typename I>
+struct SmallArgs {
+    const I *prefix;
+    const double *ladder;
+    const BondDev *bonds;
+    int nb, N, A, two_s, steps, reorth;
+    I dim;
+    double tol;
+    const double *v0;
+    T *buf[3];
+    T *V;                    // [steps][dim] normalized v_j (full reorthogonalization)
+    uint64_t *states;        // [dim] decoded states, filled at the start of the run
+    double *alpha, *beta, *hc;
+    LzDev *lz;
+    const double *coef;      // recompute pass: c_k, else nullptr
+    double *psi;
+};
+
+__device__ __forceinline__ double block_bcast(double v, double *red, double *slot) {
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) *slot = v;
+    __syncthreads();
+    const double r = *slot;
+    __syncthreads();
+    return r;
+}
+
+template <typename T, typename I, int B>
+__global__ __launch_bounds__(kSmallBlock) void lanczos_small_kernel(const SmallArgs<T, I> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    __shared__ double slot;
+    const int plen = a.N * (a.A + 1) * (a.two_s + 1);
+    I *P = reinterpret_cast<I *>(smem);
+    T *F = reinterpret_cast<T *>(smem + ((plen * sizeof(I) + 15) / 16) * 16);
+    for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = a.prefix[t];
+    for (int t = threadIdx.x; t < a.two_s + 2; t += blockDim.x) F[t] = (T)a.ladder[t];
+    __syncthreads();
+    const Prefix<I> pv{P, a.A + 1, a.two_s + 1};
+    const I n = a.dim;
+    const I tid = threadIdx.x, nt = blockDim.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+
+    double s = 0.0;
+    for (I i = tid; i < n; i += nt) s += a.v0[i] * a.v0[i];
+    s = block_bcast(s, red, &slot);
+    if (threadIdx.x == 0) {
+        a.lz->tol = a.tol;
+        a.lz->norm0 = sqrt(s);
+        a.lz->bad_start = !(s > 0.0);
+        a.lz->stopped = a.lz->bad_start ? -1 : 0;
+        a.lz->psi_norm = 0.0;
+    }
+    if (!(s > 0.0)) return;
+    const double inv0 = 1.0 / sqrt(s);
+    for (I i = tid; i < n; i += nt) {
+        const T v = (T)(a.v0[i] * inv0);
+        a.buf[0][i] = v;
+        if (a.reorth) a.V[i] = v;
+        if (a.psi) a.psi[i] = 0.0;
+        a.states[i] = unrank_state<I, B>(i, pv, a.N, a.A, a.two_s);
+    }
+    __syncthreads();
+    double beta_prev = 0.0, scale = 0.0;
+    int stopped = 0;
+    for (int k = 0; k < a.steps; ++k) {
+        const T *__restrict__ vk = a.buf[k % 3];
+        const T *__restrict__ vp = a.buf[(k + 2) % 3];
+        T *__restrict__ w = a.buf[(k + 1) % 3];
+        // w = H v_k - beta_{k-1} v_{k-1};  alpha_k = <w, v_k>
+        double dot = 0.0;
+        for (I i = tid; i < n; i += nt) {
+            const uint64_t st = a.states[i];
+            const T xi = vk[i];
+            const T hv = row_hx<T, I, B>(st, i, xi, vk, a.bonds, a.nb, a.two_s, pv, F);
+            double wi = (double)hv;
+            if (k > 0) wi -= beta_prev * (double)vp[i];
+            const T wt = (T)wi;
+            w[i] = wt;
+            dot += (double)wt * (double)xi;
+            if (a.psi) a.psi[i] += a.coef[k] * (double)xi;
+        }
+        const double alpha = block_bcast(dot, red, &slot);
+        // w -= alpha_k v_k (rows of this thread only)
+        double ss = 0.0;
+        for (I i = tid; i < n; i += nt) {
+            const T wi = (T)((double)w[i] - alpha * (double)vk[i]);
+            w[i] = wi;
+            ss += (double)wi * (double)wi;
+        }
+        if (a.reorth) {
+            __syncthreads();
+            for (int rep = 0; rep < 2; ++rep) {
+                // h_j = <V_j, w>: one wave per j, lanes over rows, fixed tree
+                for (int j = wid; j <= k; j += nwv) {
+                    const T *__restrict__ Vj = a.V + (size_t)j * (size_t)n;
+                    double d = 0.0;
+                    for (I i = lane; i < n; i += 64) d += (double)Vj[i] * (double)w[i];
+                    d = wave_sum(d);
+                    if (lane == 0) a.hc[j] = d;
+                }
+                __syncthreads();
+                for (I i = tid; i < n; i += nt) {
+                    double acc = (double)w[i];
+                    for (int j = 0; j <= k; ++j) acc -= a.hc[j] * (double)a.V[(size_t)j * n + i];
+                    w[i] = (T)acc;
+                }
+                __syncthreads();
+            }
+            ss = 0.0;
+            for (I i = tid; i < n; i += nt) ss += (double)w[i] * (double)w[i];
+        }
+        const double beta = sqrt(block_bcast(ss, red, &slot));
+        scale = fmax(scale, fmax(fabs(alpha), beta));
+        if (threadIdx.x == 0) {
+            a.alpha[k] = alpha;
+            a.beta[k] = beta;
+            a.lz->scale = scale;
+        }
+        if (!(beta > a.tol * scale)) {
+            stopped = k + 1;
+            break;
+        }
+        const double binv = 1.0 / beta;
+        for (I i = tid; i < n; i += nt) {
+            const T v = (T)((double)w[i] * binv);
+            w[i] = v;
+            if (a.reorth && k + 1 < a.steps) a.V[(size_t)(k + 1) * n + i] = v;
+        }
+        beta_prev = beta;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.lz->stopped = stopped;
+    if (a.psi) {
+        __syncthreads();
+        double q = 0.0;
+        for (I i = tid; i < n; i += nt) q += a.psi[i] * a.psi[i];
+        const double nrm = sqrt(block_bcast(q, red, &slot));
+        if (threadIdx.x == 0) a.lz->psi_norm = nrm;
+        if (nrm > 0.0)
+            for (I i = tid; i < n; i += nt) a.psi[i] /= nrm;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
 static thread_local bool g_timing = false;
@@ -304,7 +477,7 @@ static thread_local int g_hx_launches = 0;
 struct Run {
     Basis *b;
     const Couplings *c;
-    int steps, prec, reorth, kernel, use_graph;
+    int steps, prec, reorth, kernel, use_graph, small;
     double tol;
     Layout L;
     unsigned char *w;
@@ -353,8 +526,8 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
             for (int rep = 0; rep < 2; ++rep) {
                 hipLaunchKernelGGL(reorth_dots<T>, dim3(G, k + 1), dim3(kBlock), 0, R.st, V,
                                    wn, n, k + 1, partial, lz);
-                hipLaunchKernelGGL(reorth_finish, dim3(1), dim3(kBlock), 0, R.st, partial, G,
-                                   k + 1, hc, lz);
+                hipLaunchKernelGGL(reorth_finish, dim3(k + 1), dim3(64), 0, R.st, partial, G,
+                                   hc, lz);
                 hipLaunchKernelGGL(reorth_update<T>, dim3(G), dim3(kBlock), 0, R.st, V, wn, n,
                                    k + 1, hc, lz);
             }
@@ -363,6 +536,75 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
         }
         hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G, alpha,
                            beta, sigma, cprev, k);
+    }
+    HM_HIP(hipGetLastError());
+    return HM_OK;
+}
+
+// Waits for the run and copies its results to the host.
+static int collect(const Run &R, double *alpha_h, double *beta_h, int *steps_done) {
+    HM_HIP(hipGetLastError());
+    HM_HIP(hipStreamSynchronize(R.st));
+    LzDev hlz;
+    HM_HIP(hipMemcpy(&hlz, R.w + R.L.lz, sizeof hlz, hipMemcpyDeviceToHost));
+    if (hlz.bad_start) return fail(HM_EINVAL, "start vector has zero norm");
+    const int done = hlz.stopped > 0 ? hlz.stopped : R.steps;
+    if (alpha_h)
+        HM_HIP(hipMemcpy(alpha_h, R.w + R.L.alpha, sizeof(double) * done, hipMemcpyDeviceToHost));
+    if (beta_h)
+        HM_HIP(hipMemcpy(beta_h, R.w + R.L.beta, sizeof(double) * done, hipMemcpyDeviceToHost));
+    if (alpha_h) std::fill(alpha_h + done, alpha_h + R.steps, 0.0);
+    if (beta_h) std::fill(beta_h + done, beta_h + R.steps, 0.0);
+    *steps_done = done;
+    return HM_OK;
+}
+
+template <typename T, typename I, int B>
+static void launch_small_b(const Run &R) {
+    const Basis *b = R.b;
+    SmallArgs<T, I> a{};
+    a.prefix = (const I *)b->d_prefix;
+    a.ladder = b->d_ladder;
+    a.bonds = R.c->dev;
+    a.nb = R.c->nb;
+    a.N = b->N;
+    a.A = b->A;
+    a.two_s = b->two_s;
+    a.steps = R.steps;
+    a.reorth = R.reorth;
+    a.dim = (I)b->dim;
+    a.tol = R.tol;
+    a.v0 = R.v0;
+    a.buf[0] = (T *)(R.w + R.L.r0);
+    a.buf[1] = (T *)(R.w + R.L.r1);
+    a.buf[2] = (T *)(R.w + R.L.r2);
+    a.V = (T *)(R.w + R.L.V);
+    a.states = (uint64_t *)(R.w + R.L.states);
+    a.alpha = (double *)(R.w + R.L.alpha);
+    a.beta = (double *)(R.w + R.L.beta);
+    a.hc = (double *)(R.w + R.L.hcoef);
+    a.lz = (LzDev *)(R.w + R.L.lz);
+    a.coef = R.psi ? (const double *)(R.w + R.L.coef) : nullptr;
+    a.psi = R.psi;
+    const size_t lds = ((prefix_bytes(b) + 15) / 16) * 16 + (b->two_s + 2) * sizeof(double);
+    hipLaunchKernelGGL((lanczos_small_kernel<T, I, B>), dim3(1), dim3(kSmallBlock), lds, R.st,
+                       a);
+}
+
+template <typename T>
+static int launch_small(const Run &R) {
+    HM_TRY(check_lds(R.b));
+    if (!R.b->idx32) return fail(HM_ERANGE, "the one-workgroup run needs 32-bit prefix tables");
+    switch (R.b->bits) {
+        case 1: launch_small_b<T, uint32_t, 1>(R); break;
+        case 2: launch_small_b<T, uint32_t, 2>(R); break;
+        case 3: launch_small_b<T, uint32_t, 3>(R); break;
+        case 4: launch_small_b<T, uint32_t, 4>(R); break;
+        case 5: launch_small_b<T, uint32_t, 5>(R); break;
+        case 6: launch_small_b<T, uint32_t, 6>(R); break;
+        case 7: launch_small_b<T, uint32_t, 7>(R); break;
+        case 8: launch_small_b<T, uint32_t, 8>(R); break;
+        default: return fail(HM_ERANGE, "bits per digit %d unsupported", R.b->bits);
     }
     HM_HIP(hipGetLastError());
     return HM_OK;
@@ -380,7 +622,11 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
     if (R.psi) {
         HM_HIP(hipMemcpyAsync(R.w + R.L.coef, R.coef_host, sizeof(double) * R.steps,
                               hipMemcpyHostToDevice, R.st));
-        hipLaunchKernelGGL(zero_f64, dim3(G), dim3(kBlock), 0, R.st, R.psi, n);
+        if (!R.small) hipLaunchKernelGGL(zero_f64, dim3(G), dim3(kBlock), 0, R.st, R.psi, n);
+    }
+    if (R.small) {
+        HM_TRY(launch_small<T>(R));
+        return collect(R, alpha_h, beta_h, steps_done);
     }
     hipLaunchKernelGGL(sumsq_kernel<double>, dim3(G), dim3(kBlock), 0, R.st, R.v0, n, partial,
                        (const int *)nullptr);
@@ -436,20 +682,8 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
         hipLaunchKernelGGL(scale_psi, dim3(G), dim3(kBlock), 0, R.st, R.psi, n, lz);
     }
     if (timing) HM_HIP(hipEventRecord(hi, R.st));
-    HM_HIP(hipGetLastError());
-    HM_HIP(hipStreamSynchronize(R.st));
-
-    LzDev hlz;
-    HM_HIP(hipMemcpy(&hlz, lz, sizeof hlz, hipMemcpyDeviceToHost));
-    if (hlz.bad_start) return fail(HM_EINVAL, "start vector has zero norm");
-    const int done = hlz.stopped > 0 ? hlz.stopped : R.steps;
-    if (alpha_h)
-        HM_HIP(hipMemcpy(alpha_h, R.w + R.L.alpha, sizeof(double) * done, hipMemcpyDeviceToHost));
-    if (beta_h)
-        HM_HIP(hipMemcpy(beta_h, R.w + R.L.beta, sizeof(double) * done, hipMemcpyDeviceToHost));
-    if (alpha_h) std::fill(alpha_h + done, alpha_h + R.steps, 0.0);
-    if (beta_h) std::fill(beta_h + done, beta_h + R.steps, 0.0);
-    *steps_done = done;
+    HM_TRY(collect(R, alpha_h, beta_h, steps_done));
+    const int done = *steps_done;
     if (timing) {
         double hx = 0.0;
         for (int k = 0; k < done; ++k) {
@@ -470,8 +704,11 @@ static int check_opts(const Basis *b, const hm_lanczos_opts *o) {
     if (!o) return fail(HM_EINVAL, "opts is null");
     if (o->precision != HM_PREC_F64 && o->precision != HM_PREC_F32_MIXED)
         return fail(HM_EINVAL, "unknown precision %d", o->precision);
-    if (o->kernel < 0 || o->kernel > 2) return fail(HM_EINVAL, "unknown kernel %d", o->kernel);
-    if (choose_kernel(b, nullptr, o->kernel) < 0)
+    if (o->kernel < 0 || o->kernel > 3) return fail(HM_EINVAL, "unknown kernel %d", o->kernel);
+    if (o->kernel == 3 && b->dim > kSmallMaxDim)
+        return fail(HM_ERANGE, "the one-workgroup run takes at most %lld rows",
+                    (long long)kSmallMaxDim);
+    if (o->kernel != 3 && choose_kernel(b, nullptr, o->kernel) < 0)
         return fail(HM_EINVAL, "spin-1/2 block kernel not applicable to this basis");
     return HM_OK;
 }
@@ -486,10 +723,12 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     HM_TRY(check_opts(b, o));
     const Couplings *c = nullptr;
     HM_TRY(get_couplings(b, J, &c));
-    const int kernel = choose_kernel(b, c, o->kernel);
+    const bool small = o->kernel == 3 || (o->kernel == 0 && !g_timing && b->dim <= kSmallAutoDim);
+    const int kernel = small ? 1 : choose_kernel(b, c, o->kernel);
     if (kernel < 0) return fail(HM_ERANGE, "block kernel tables too large for these couplings");
     if (kernel == 2) HM_TRY(half_prepare_tables(b, c));
     Run R{};
+    R.small = small ? 1 : 0;
     R.b = b;
     R.c = c;
     R.steps = steps;

@@ -171,15 +171,18 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_lanczos_ring12_matches_oracle(use_graph):
+# Lanczos paths: kernel 0 picks the one-workgroup run at these sizes, kernel 1
+# forces the multi-kernel step (generic H x), kernel 3 the one-workgroup run.
+@pytest.mark.parametrize("use_graph,kernel", [(False, 1), (True, 1), (True, 0), (False, 3)])
+def test_lanczos_ring12_matches_oracle(use_graph, kernel):
     """N=12 ring, 120 steps with full reorthogonalization, FP64."""
     from paper_0706_3293_amd import inputs
     g = _golden("ring12_oracle.json")
     b = _basis(12, 1, 6)
     J = inputs.ring_couplings(12, -1.0)
     v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
-    res = b.lanczos(J, v0, 120, precision="f64", full_reorth=True, use_graph=use_graph)
+    res = b.lanczos(J, v0, 120, precision="f64", full_reorth=True, use_graph=use_graph,
+                    kernel=kernel)
     assert res.steps_done == 120
     assert abs(res.E0 - g["E0"]) <= 1e-10 * abs(g["E0"])
     assert abs(res.E0 - (-5.387390917445204)) < 1e-11
@@ -190,29 +193,32 @@ def test_lanczos_ring12_matches_oracle(use_graph):
     assert np.abs(res.beta[:40] - g["beta"][:40]).max() < 1e-12
 
 
-def test_lanczos_ring12_mixed():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_lanczos_ring12_mixed(kernel):
     from paper_0706_3293_amd import inputs
     g = _golden("ring12_oracle.json")
     b = _basis(12, 1, 6)
     J = inputs.ring_couplings(12, -1.0)
     v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
-    res = b.lanczos(J, v0, 120, precision="f32_mixed", full_reorth=True)
+    res = b.lanczos(J, v0, 120, precision="f32_mixed", full_reorth=True, kernel=kernel)
     assert abs(res.E0 - g["E0"]) <= 1e-7 * abs(g["E0"])
 
 
 @pytest.mark.parametrize("N", [12, 16, 20])
 @pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
-def test_lanczos_majumdar_ghosh(N, precision):
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_lanczos_majumdar_ghosh(N, precision, kernel):
     from paper_0706_3293_amd import inputs
     b = _basis(N, 1, N // 2)
     J = inputs.ring_couplings(N, -1.0, -0.5)
     v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
-    res = b.lanczos(J, v0, 150, precision=precision)
+    res = b.lanczos(J, v0, 150, precision=precision, kernel=kernel)
     tol = 1e-10 if precision == "f64" else 1e-7
     assert abs(res.E0 + 3 * N / 8) <= tol * 3 * N / 8
 
 
-def test_lanczos_general_spin_vs_oracle():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_lanczos_general_spin_vs_oracle(kernel):
     import oracle
     rng = np.random.default_rng(5)
     for N, two_s, A in ((9, 2, 9), (6, 3, 9), (5, 4, 10)):
@@ -222,31 +228,35 @@ def test_lanczos_general_spin_vs_oracle():
         v0 = rng.uniform(-1, 1, sub.dim)
         steps = min(60, sub.dim)
         ref = oracle.lanczos(sub, J, v0, steps, full_reorth=True)
-        res = b.lanczos(J, torch.tensor(v0, device="cuda"), steps, full_reorth=True)
+        res = b.lanczos(J, torch.tensor(v0, device="cuda"), steps, full_reorth=True,
+                        kernel=kernel)
         assert res.steps_done == ref["steps_done"]
         assert abs(res.E0 - ref["E0"]) <= 1e-10 * abs(ref["E0"])
         k = min(20, res.steps_done)
         assert np.abs(res.alpha[:k] - ref["alpha"][:k]).max() < 1e-10
 
 
-def test_lanczos_breakdown():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_lanczos_breakdown(kernel):
     """Dimer singlet start: beta_1 = 0, one step, E0 = -3/4."""
     b = _basis(2, 1, 1)
     J = np.array([[0.0, -1.0], [-1.0, 0.0]])
     v0 = torch.tensor([1.0, -1.0], dtype=torch.float64, device="cuda")
     for graph in (False, True):
-        res = b.lanczos(J, v0, 10, use_graph=graph)
+        res = b.lanczos(J, v0, 10, use_graph=graph, kernel=kernel)
         assert res.steps_done == 1 and abs(res.E0 + 0.75) < 1e-15
-    res = b.lanczos(J, torch.tensor([0.3, 0.9], dtype=torch.float64, device="cuda"), 10)
+    res = b.lanczos(J, torch.tensor([0.3, 0.9], dtype=torch.float64, device="cuda"), 10,
+                    kernel=kernel)
     assert res.steps_done == 2 and abs(res.E0 + 0.75) < 1e-14
 
 
-def test_lanczos_zero_start_vector_rejected():
+@pytest.mark.parametrize("kernel", [0, 1, 3])
+def test_lanczos_zero_start_vector_rejected(kernel):
     from paper_0706_3293_amd import _lib, inputs
     b = _basis(8, 1, 4)
     J = inputs.ring_couplings(8, -1.0)
     with pytest.raises(_lib.HMError):
-        b.lanczos(J, torch.zeros(b.dim, dtype=torch.float64, device="cuda"), 5)
+        b.lanczos(J, torch.zeros(b.dim, dtype=torch.float64, device="cuda"), 5, kernel=kernel)
 
 
 def test_lanczos_is_bitwise_reproducible():
@@ -259,7 +269,8 @@ def test_lanczos_is_bitwise_reproducible():
     assert np.array_equal(r1.alpha, r2.alpha) and np.array_equal(r1.beta, r2.beta)
 
 
-def test_ground_state_and_bond_corr_small():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_ground_state_and_bond_corr_small(kernel):
     import oracle
     from paper_0706_3293_amd import inputs, tridiag_lowest
     N = 12
@@ -269,9 +280,9 @@ def test_ground_state_and_bond_corr_small():
     v0 = inputs.start_vector(sub.dim, 0)
     ref = oracle.ground_state(sub, J, v0, 120, full_reorth=True)
     v0d = torch.tensor(v0, device="cuda")
-    res = b.lanczos(J, v0d, 120, full_reorth=True)
+    res = b.lanczos(J, v0d, 120, full_reorth=True, kernel=kernel)
     E0, c = tridiag_lowest(res.alpha, res.beta)
-    psi, a2, b2 = b.ritz(J, v0d, res.steps_done, c, full_reorth=True)
+    psi, a2, b2 = b.ritz(J, v0d, res.steps_done, c, full_reorth=True, kernel=kernel)
     assert np.array_equal(a2, res.alpha) and np.array_equal(b2, res.beta)
     p = psi.cpu().numpy()
     assert abs(abs(p @ ref["psi"]) - 1) < 1e-10
@@ -296,3 +307,33 @@ def test_bond_corr_general_spin():
     C = b.bond_corr(bonds, torch.tensor(psi, device="cuda"))
     C_ref = oracle.bond_correlations(sub, psi, bonds)
     assert np.abs(C - C_ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
+@pytest.mark.parametrize("reorth", [False, True])
+def test_one_workgroup_run_matches_multi_kernel_run(precision, reorth):
+    """The one-workgroup Lanczos (kernel 3) against the multi-kernel step
+    (kernel 1) on the same inputs, s = 1/2 and s = 1, and bitwise
+    reproducibility of the one-workgroup run."""
+    from paper_0706_3293_amd import inputs
+    for N, two_s, A, J in ((16, 1, 8, inputs.ring_couplings(16, -1.0, -0.3)),
+                           (9, 2, 9, _rand_J(9, np.random.default_rng(9)))):
+        print("one-workgroup run", N, two_s, A, precision, reorth, flush=True)
+        b = _basis(N, two_s, A)
+        v0 = torch.tensor(inputs.start_vector(b.dim, 1), device="cuda")
+        r3 = b.lanczos(J, v0, 60, precision=precision, full_reorth=reorth, kernel=3)
+        r1 = b.lanczos(J, v0, 60, precision=precision, full_reorth=reorth, kernel=1)
+        tol = 1e-10 if precision == "f64" else 2e-6
+        assert r3.steps_done == r1.steps_done
+        assert abs(r3.E0 - r1.E0) <= tol * abs(r1.E0)
+        assert np.abs(r3.alpha[:15] - r1.alpha[:15]).max() <= tol * np.abs(r1.alpha).max()
+        again = b.lanczos(J, v0, 60, precision=precision, full_reorth=reorth, kernel=3)
+        assert np.array_equal(again.alpha, r3.alpha) and np.array_equal(again.beta, r3.beta)
+
+
+def test_one_workgroup_run_size_limit():
+    from paper_0706_3293_amd import _lib, inputs
+    b = _basis(24, 1, 12)                     # 2.7 M rows: above the one-workgroup limit
+    v0 = torch.ones(b.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(_lib.HMError):
+        b.lanczos(inputs.ring_couplings(24, -1.0), v0, 2, kernel=3)
