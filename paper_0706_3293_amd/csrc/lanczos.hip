@@ -319,7 +319,7 @@ __global__ void zero_f64(double *__restrict__ x, int64_t n) {
 // stored normalized.  One compute unit does all the row work, so the run pays
 // off only while that work stays below the launch costs it saves: measured,
 // up to about 2000 rows without reorthogonalization, and about 1000 rows with
-// it (where it takes a third of the multi-kernel time).
+// it (where it takes about half of the multi-kernel time).
 // ---------------------------------------------------------------------------
 constexpr int kSmallBlock = 1024;
 
