@@ -108,6 +108,16 @@ int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
 int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
                           int32_t rows_per_lane);
 
+/* Work split of the spin-1/2 block kernel: 1 = items of 64 rows of a block
+ * (the low-word gathers read global memory); 2 = staged blocks: one wave takes
+ * all rows of its R blocks, copies them to LDS and serves the gathers of the
+ * bonds inside the low word from there (needs C(K, K/2) <= 512, i.e. K <= 11,
+ * 32-bit indices, rows_per_lane <= 4 (<= 2 when K = 11); otherwise the first
+ * device use fails with HM_EINVAL); 0 = automatic.  Must be called before the
+ * first device use of the handle.  The two give bitwise equal results.
+ * HM_EINVAL: mode outside 0..2 or tables already built. */
+int hm_basis_set_staging(hm_basis h, int32_t mode);
+
 /* ---------------------------------------------------------------------------
  * Decoding i -> |a_1..a_N> (Sec. 3.1) and encoding |a> -> i (Sec. 3.2) on the
  * host.  digits is a host array of N bytes, digits[u] = a_{u+1}.

@@ -50,6 +50,7 @@ SIGNATURES = {
     "hm_basis_dim": (_i32, [_vp, _i64p]),
     "hm_basis_info": (_i32, [_vp, _i32p, _i32p, _i32p, _i32p]),
     "hm_basis_set_schedule": (_i32, [_vp, _i32, _i32, _i32]),
+    "hm_basis_set_staging": (_i32, [_vp, _i32]),
     "hm_unrank": (_i32, [_vp, _i64, _u8p]),
     "hm_rank": (_i32, [_vp, _u8p, _i64p]),
     "hm_unrank_dev": (_i32, [_vp, _vp, _i64, _vp, _vp]),

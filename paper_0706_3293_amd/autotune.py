@@ -1,7 +1,7 @@
 """Autotuner for the spin-1/2 block kernel's schedule.
 
 For a given problem (N, M, couplings, element type) every candidate schedule
-(low bits K, workgroup size, rows per lane) is built on a fresh basis handle
+(low bits K, workgroup size, rows per lane, work split) is built on a fresh basis handle
 and timed with HIP events over a few H x applications on the current stream;
 the fastest is returned and remembered in a JSON cache keyed by the problem.
 A chosen schedule is fixed for the lifetime of its basis handle, so the two
@@ -22,15 +22,29 @@ DEFAULT_CACHE = os.environ.get(
 
 
 def candidates(N):
-    """Schedules worth trying for N sites (K, block threads, rows per lane)."""
+    """Schedules worth trying for N sites: (K, block threads, rows per lane,
+    staging), staging 1 = chunked items, 2 = staged blocks."""
     out = []
     for K in sorted({max(1, min(N, k)) for k in (10, 11, 12, 13, 14)}):
         if N - K > 24:
             continue
         for R in (1, 2, 4, 8):
-            out.append((K, 256, R))
-    out.append((min(N, 12), 128, 4))
+            out.append((K, 256, R, 1))
+    out.append((min(N, 12), 128, 4, 1))
+    # staged blocks need C(K, K/2) <= 512 and 32-bit indices (dim < 2^32)
+    if _indices_fit_32(N):
+        for K, rows in ((9, (1, 2, 4)), (10, (1, 2, 4)), (11, (1, 2))):
+            if K <= N and N - K <= 24:
+                for R in rows:
+                    out.append((K, 256, R, 2))
     return out
+
+
+def _indices_fit_32(N):
+    """Whether the M = 0 (or nearest) subspace of N spins 1/2 has fewer than
+    2^32 states, the condition for 32-bit indices."""
+    from math import comb
+    return comb(N, N // 2) < (1 << 32)
 
 
 def _key(N, two_M, J, dtype):
@@ -52,7 +66,8 @@ def time_apply(b, J, x, y, reps):
 
 
 def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbose=False):
-    """Best (K, block, R) for H x with these couplings; results are cached."""
+    """Best (K, block, R, staging) for H x with these couplings; results are
+    cached (entries of an older three-field format are tuned again)."""
     key = _key(N, two_M, J, str(dtype))
     table = {}
     if cache and os.path.exists(cache):
@@ -61,7 +76,7 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-    if key in table:
+    if key in table and len(table[key]["schedule"]) == 4:
         return tuple(table[key]["schedule"])
     probe = Basis(N, two_s=1, two_M=two_M)
     x = torch.rand(probe.dim, dtype=dtype, device="cuda")
@@ -74,8 +89,8 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
         ms = time_apply(b, J, x, y, reps)
         trials.append((sched, ms))
         if verbose:
-            print(f"[autotune] K={sched[0]} block={sched[1]} R={sched[2]}: {ms:.3f} ms",
-                  flush=True)
+            print(f"[autotune] K={sched[0]} block={sched[1]} R={sched[2]} "
+                  f"staging={sched[3]}: {ms:.3f} ms", flush=True)
         if ms < best_ms:
             best, best_ms = sched, ms
         del b

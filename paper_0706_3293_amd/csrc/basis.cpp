@@ -300,6 +300,17 @@ int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
     return HM_OK;
 }
 
+int hm_basis_set_staging(hm_basis h, int32_t mode) {
+    hm::clear_error();
+    if (!h) return fail(HM_EINVAL, "null handle");
+    hm::Basis &b = h->impl;
+    std::lock_guard<std::mutex> lock(b.mu);
+    if (b.half_tables) return fail(HM_EINVAL, "staging must be set before the first device use");
+    if (mode < 0 || mode > 2) return fail(HM_EINVAL, "staging mode %d outside 0..2", mode);
+    b.half_staging = mode;
+    return HM_OK;
+}
+
 int hm_unrank(hm_basis h, int64_t i, uint8_t *digits) {
     hm::clear_error();
     if (!h || !digits) return fail(HM_EINVAL, "null argument");

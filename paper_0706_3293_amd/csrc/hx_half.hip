@@ -58,7 +58,7 @@ struct BondGroup {
 
 // Per-basis tables of the block kernel.
 struct HalfTables {
-    int K = 0, block = 256, R = 1;
+    int K = 0, block = 256, R = 1, C = 0;   // C > 0: staged blocks of 64 C entries
     int64_t n_items = 0, n_groups = 0;
     std::vector<uint64_t> off_host;
     uint16_t *d_rankL = nullptr, *d_unrankL = nullptr;
@@ -278,6 +278,264 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
     }
 }
 
+// Read-only tables seen through the constant address space.
+template <typename T>
+using Const = const __attribute__((address_space(4))) T;
+template <typename T>
+__device__ __forceinline__ const Const<T> *as_const(const T *p) {
+    return (const Const<T> *)p;
+}
+template <typename T> __device__ __forceinline__ T coefc(const Const<BondGroup> &g, int q);
+template <> __device__ __forceinline__ float coefc<float>(const Const<BondGroup> &g, int q) {
+    return g.c32[q];
+}
+template <> __device__ __forceinline__ double coefc<double>(const Const<BondGroup> &g, int q) {
+    return g.c64[q];
+}
+
+// Staged variant.  Work item = one group of R high words of one popcount
+// class with ALL rows of their blocks: the block size S = C(K, aL) is at most
+// 64 C, and lane r owns the low words of ranks r, r + 64, ..., r + 64 (C - 1).
+// The wave first copies the R blocks of x into its private LDS slice (the
+// loads it needs anyway for x_i), so the gathers of the bonds inside the low
+// word, which scatter over the block, read LDS instead of going through the
+// vector memory pipeline; high-word and straddling bonds gather from global
+// memory as in hx_half_kernel (coalesced for high-word bonds).  Same
+// arithmetic per row as hx_half_kernel: acc accumulates the
+// bonds in the same order, so both kernels give bitwise equal results.
+// Shared state of one wave of the staged kernel.
+template <typename T, typename I>
+struct StagedWave {
+    const uint16_t *rankL, *unrankL;
+    T *xs;                              // this wave's LDS slice
+    const Const<BondGroup> *gl, *gh, *gs;
+    const Const<I> *nbr;
+    const T *x;
+    T *y;
+    const T *prev;
+    T *store;
+    double sigma, cprev;
+    T shift;
+    int lane;
+};
+
+// One item (R blocks of class size S) with J live 64-row slices per block
+// (J = ceil(S / 64) rounded up to a power of two, J <= C).
+template <typename T, typename I, int R, int C, int J, bool DOT, bool STORE>
+__device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWave<T, I> &w,
+                                            const uint32_t (&hs)[R], const bool (&valid)[R],
+                                            const I (&off)[R], int S, int cs, double &dot) {
+    constexpr int kSlice = 64 * C;
+    uint32_t L[J], rb[J];
+    bool live[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int r0 = w.lane + 64 * j;
+        live[j] = r0 < S;
+        const int r = live[j] ? r0 : 0;            // dead lanes shadow row 0
+        rb[j] = (uint32_t)r;
+        L[j] = w.unrankL[cs + r];
+    }
+    const Const<I> *nb[R];
+    T xi[R][J], acc[R][J];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        nb[m] = w.nbr + (size_t)hs[m] * g.width;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            xi[m][j] = load_at(w.x + off[m], rb[j] * (uint32_t)sizeof(T));
+            acc[m][j] = 0;
+        }
+    }
+    // stage this item's blocks.  The slice is private to the wave and a
+    // wave's LDS accesses complete in program order, so the previous item's
+    // reads are done and the writes below are seen by the reads after them;
+    // the wave barrier keeps the compiler from moving LDS accesses across.
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < R; ++m)
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (live[j]) w.xs[m * kSlice + rb[j]] = xi[m][j];
+    __builtin_amdgcn_wave_barrier();
+    // bonds inside the low word: LDS gathers
+    for (int k = 0; k < g.nLg; ++k) {
+        const Const<BondGroup> &G = w.gl[k];
+        uint32_t mk[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) mk[q] = G.m1[q];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            uint32_t idx[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                const uint32_t t2 = w.rankL[L[j] ^ mk[q]];
+                idx[q] = __popc(L[j] & mk[q]) == 1 ? t2 : rb[j];
+            }
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) xj[q] = w.xs[m * kSlice + idx[q]];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+            }
+        }
+    }
+    // bonds inside the high word: coalesced global gathers (the own block,
+    // an L1 hit, when the bond cannot flip for h_m)
+    for (int k = 0; k < g.nHg; ++k) {
+        const Const<BondGroup> &G = w.gh[k];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            I o[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) o[q] = nb[m][k * kGroup + q];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q)
+                    xj[q] = load_at(w.x + o[q], rb[j] * (uint32_t)sizeof(T));
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+            }
+        }
+    }
+    // bonds with one site in each word: uniform high bit, per-lane low bit
+    for (int k = 0; k < g.nSg; ++k) {
+        const Const<BondGroup> &G = w.gs[k];
+        uint32_t ml[kGroup];
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q) ml[q] = G.m1[q];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            uint32_t rk[kGroup], lb[kGroup];
+#pragma unroll
+            for (int q = 0; q < kGroup; ++q) {
+                rk[q] = w.rankL[L[j] ^ ml[q]];
+                lb[q] = L[j] & ml[q];
+            }
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const Const<I> *nbs = nb[m] + (g.nHg + k) * kGroup;
+                const I own = off[m] + (I)rb[j];
+                T xj[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) {
+                    const uint32_t want = ml[q] == 0 ? 1u : ((hs[m] & G.m2[q]) ? 0u : ml[q]);
+                    xj[q] = w.x[lb[q] == want ? nbs[q] + (I)rk[q] : own];
+                }
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            if (live[j] && valid[m]) {
+                const I row = off[m] + (I)rb[j];
+                const T hv = w.shift * xi[m][j] + acc[m][j];
+                double v = w.sigma * (double)hv;
+                if (w.prev) v -= w.cprev * (double)w.prev[row];
+                const T vt = (T)v;
+                w.y[row] = vt;
+                if constexpr (DOT) dot += (double)vt * (w.sigma * (double)xi[m][j]);
+                if constexpr (STORE) w.store[row] = (T)(w.sigma * (double)xi[m][j]);
+            }
+        }
+    }
+}
+
+template <typename T, typename I, int R, int C, bool DOT, bool STORE>
+__global__ __launch_bounds__(256) void hx_half_staged_kernel(
+    const HalfArgs<I> g, const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ prev,
+    const double *__restrict__ sigma_p, const double *__restrict__ cprev_p,
+    double *__restrict__ partial, T *__restrict__ store, const int *__restrict__ stopped) {
+    if (stopped && *stopped) return;
+    extern __shared__ __align__(16) uint16_t lds16[];
+    __shared__ double red[16];
+    const int nlow = 1 << g.K;
+    uint16_t *rankL = lds16;
+    uint16_t *unrankL = lds16 + nlow;
+    for (int t = threadIdx.x; t < nlow; t += blockDim.x) {
+        rankL[t] = g.rankL[t];
+        unrankL[t] = g.unrankL[t];
+    }
+    __syncthreads();
+
+    StagedWave<T, I> w;
+    w.rankL = rankL;
+    w.unrankL = unrankL;
+    w.xs = reinterpret_cast<T *>(lds16 + 2 * nlow) + (size_t)(threadIdx.x >> 6) * (R * 64 * C);
+    // the tables are read-only for the whole launch: reading them through
+    // the constant address space lets wave-uniform reads be scalar loads even
+    // though the wave writes LDS in between
+    w.gl = as_const(g.groups);
+    w.gh = w.gl + g.nLg;
+    w.gs = w.gl + g.nLg + g.nHg;
+    w.nbr = as_const(g.nbr);
+    w.x = x;
+    w.y = y;
+    w.prev = prev;
+    w.store = store;
+    w.sigma = sigma_p ? *sigma_p : 1.0;
+    w.cprev = cprev_p ? *cprev_p : 0.0;
+    w.shift = (T)g.shift;
+    w.lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    uint32_t first = 0, last = g.n_items, stride = gridDim.x * nw, wl;
+    if (gridDim.x % kXcds == 0) {
+        const uint32_t x8 = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+        first = (uint32_t)((uint64_t)g.n_items * x8 / kXcds);
+        last = (uint32_t)((uint64_t)g.n_items * (x8 + 1) / kXcds);
+        stride = per * nw;
+        wl = (blockIdx.x / kXcds) * nw + (threadIdx.x >> 6);
+    } else {
+        wl = blockIdx.x * nw + (threadIdx.x >> 6);
+    }
+    wl = __builtin_amdgcn_readfirstlane(wl);
+    first = __builtin_amdgcn_readfirstlane(first);
+    last = __builtin_amdgcn_readfirstlane(last);
+    stride = __builtin_amdgcn_readfirstlane(stride);
+    const Const<uint32_t> *hgroups = as_const(g.hgroups);
+    const Const<I> *offs = as_const(g.off);
+    double dot = 0.0;
+    for (uint32_t it = first + wl; it < last; it += stride) {
+        const Const<uint32_t> *hg = hgroups + (size_t)it * R;
+        uint32_t hs[R];
+        bool valid[R];
+        I off[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) hs[m] = hg[m];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            valid[m] = hs[m] != kNoHigh;
+            if (!valid[m]) hs[m] = hs[0];
+            off[m] = offs[hs[m]];
+        }
+        const int aL = g.A - __popc(hs[0]);
+        const int S = g.class_size[aL];
+        const int cs = g.class_start[aL];
+        // live 64-row slices, rounded up to a power of two (wave-uniform)
+        const int nj = (S + 63) >> 6;
+        if (C >= 8 && nj > 4)
+            staged_item<T, I, R, C, (C >= 8 ? 8 : 1), DOT, STORE>(g, w, hs, valid, off, S, cs, dot);
+        else if (C >= 4 && nj > 2)
+            staged_item<T, I, R, C, (C >= 4 ? 4 : 1), DOT, STORE>(g, w, hs, valid, off, S, cs, dot);
+        else if (C >= 2 && nj > 1)
+            staged_item<T, I, R, C, 2, DOT, STORE>(g, w, hs, valid, off, S, cs, dot);
+        else
+            staged_item<T, I, R, C, 1, DOT, STORE>(g, w, hs, valid, off, S, cs, dot);
+    }
+    if constexpr (DOT) {
+        const double s = block_sum(dot, red);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -319,6 +577,38 @@ static int64_t item_count(const Basis *b) {
     return n;
 }
 
+// Staged blocks: entries per lane (C) for a block of up to C(K, K/2) rows,
+// 0 if the largest block does not fit 8 per lane.
+static int staged_entries(int K) {
+    const int64_t smax = binom(K, K / 2);
+    return smax <= 128 ? 2 : (smax <= 256 ? 4 : (smax <= 512 ? 8 : 0));
+}
+
+static bool staged_possible(const Basis *b) {
+    const int C = staged_entries(low_bits_of(b)), R = rows_of(b);
+    return C > 0 && b->idx32 && R <= (C == 8 ? 2 : 4);
+}
+
+// Whether the staged work split runs (a function of the basis and its
+// schedule only, so workspace sizes can be computed before the tables).
+static bool staged_of(const Basis *b) {
+    if (b->half_staging == 1) return false;
+    if (b->half_staging == 2) return true;
+    return false;
+}
+
+// Number of high-word groups (work items of the staged split).
+static int64_t group_count(const Basis *b) {
+    const int K = low_bits_of(b), nh = b->N - K, R = rows_of(b);
+    int64_t n = 0;
+    for (int ph = 0; ph <= nh; ++ph) {
+        const int aL = b->A - ph;
+        if (aL < 0 || aL > K) continue;
+        n += (binom(nh, ph) + R - 1) / R;
+    }
+    return n;
+}
+
 static int grid_for_items(int64_t n_items, int block) {
     const int nw = block / 64;
     int64_t g = (n_items + nw - 1) / nw;
@@ -329,7 +619,9 @@ static int grid_for_items(int64_t n_items, int block) {
 }
 
 // Workgroups of the block kernel (= FP64 partial sums it writes).
-int hx_half_grid(const Basis *b) { return grid_for_items(item_count(b), block_of(b)); }
+int hx_half_grid(const Basis *b) {
+    return grid_for_items(staged_of(b) ? group_count(b) : item_count(b), block_of(b));
+}
 
 static hipError_t upload(void **dst, const void *src, size_t bytes) {
     hipError_t e = hipMalloc(dst, bytes);
@@ -348,10 +640,15 @@ static int half_prepare(Basis *b, HalfTables **out) {
     const int K = low_bits_of(b), R = rows_of(b);
     if (K > kHalfMaxK || N - K > kHalfMaxHighBits || K < 1 || K > N)
         return fail(HM_EINVAL, "block kernel: low bits K=%d unsupported for N=%d", K, N);
+    if (staged_of(b) && !staged_possible(b))
+        return fail(HM_EINVAL,
+                    "staged block kernel needs C(K, K/2) <= 512, 32-bit indices and at most "
+                    "4 rows per lane (2 when K = 11); K=%d, R=%d", K, R);
     auto *t = new HalfTables;
     t->K = K;
     t->R = R;
     t->block = block_of(b);
+    t->C = staged_of(b) ? staged_entries(K) : 0;
     const int nlow = 1 << K;
     std::vector<uint16_t> rankL(nlow), unrankL(nlow);
     std::vector<int> fill(K + 1, 0);
@@ -576,6 +873,46 @@ static void launch_r(const HalfTables *t, const HalfArgs<I> &g, const HxPass &p,
 #undef HM_LAUNCH
 }
 
+template <typename T, int R, int C>
+static void launch_staged(const HalfTables *t, const HalfArgs<uint32_t> &g, const HxPass &p,
+                          hipStream_t st) {
+    const int grid = grid_for_items(t->n_groups, t->block);
+    const size_t lds = 2 * sizeof(uint16_t) * ((size_t)1 << t->K) +
+                       (size_t)(t->block / 64) * R * 64 * C * sizeof(T);
+    const T *x = (const T *)p.x;
+    T *y = (T *)p.y;
+    const T *pr = (const T *)p.p;
+    T *store = (T *)p.store;
+#define HM_LAUNCH(D, S)                                                                    \
+    hipLaunchKernelGGL((hx_half_staged_kernel<T, uint32_t, R, C, D, S>), dim3(grid),       \
+                       dim3(t->block), lds, st, g, x, y, pr, p.sigma, p.cprev, p.partial, \
+                       store, p.stopped)
+    const bool dot = p.partial != nullptr, sto = store != nullptr;
+    if (!dot && !sto) HM_LAUNCH(false, false);
+    else if (dot && !sto) HM_LAUNCH(true, false);
+    else if (!dot && sto) HM_LAUNCH(false, true);
+    else HM_LAUNCH(true, true);
+#undef HM_LAUNCH
+}
+
+template <typename T>
+static void launch_staged_t(const HalfTables *t, HalfArgs<uint32_t> g, const HxPass &p,
+                            hipStream_t st) {
+    g.n_items = (uint32_t)t->n_groups;
+    if (t->C == 2) {
+        if (t->R == 1) launch_staged<T, 1, 2>(t, g, p, st);
+        else if (t->R == 2) launch_staged<T, 2, 2>(t, g, p, st);
+        else launch_staged<T, 4, 2>(t, g, p, st);
+    } else if (t->C == 4) {
+        if (t->R == 1) launch_staged<T, 1, 4>(t, g, p, st);
+        else if (t->R == 2) launch_staged<T, 2, 4>(t, g, p, st);
+        else launch_staged<T, 4, 4>(t, g, p, st);
+    } else {
+        if (t->R == 1) launch_staged<T, 1, 8>(t, g, p, st);
+        else launch_staged<T, 2, 8>(t, g, p, st);
+    }
+}
+
 template <typename T, typename I>
 static void launch_t(const HalfTables *t, const HalfBonds *hb, const Basis *b, double shift,
                      const HxPass &p, hipStream_t st) {
@@ -598,6 +935,12 @@ static void launch_t(const HalfTables *t, const HalfBonds *hb, const Basis *b, d
     for (int a = 0; a <= kHalfMaxK + 1; ++a) {
         g.class_start[a] = t->class_start[a];
         g.class_size[a] = t->class_size[a];
+    }
+    if constexpr (sizeof(I) == 4) {
+        if (t->C > 0) {
+            launch_staged_t<T>(t, g, p, st);
+            return;
+        }
     }
     switch (t->R) {
         case 1: launch_r<T, I, 1>(t, g, p, st); break;

@@ -15,11 +15,11 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _basis(N, A, K=0, block=0, R=0):
+def _basis(N, A, K=0, block=0, R=0, staging=0):
     from paper_0706_3293_amd import Basis
     b = Basis(N, two_s=1, two_M=N - 2 * A)
-    if K or block or R:
-        b.set_schedule(K, block, R)
+    if K or block or R or staging:
+        b.set_schedule(K, block, R, staging)
     return b
 
 
@@ -72,14 +72,82 @@ def test_block_kernel_matches_oracle(N, A, K, block, R, kind):
     assert np.abs(y32 - ref32).max() <= 2e-6 * scale
 
 
-@pytest.mark.parametrize("N", [28, 32])
-def test_block_kernel_full_size_sampled_rows(N):
-    """Workload sizes: sampled rows against the oracle, FP64 and FP32."""
+STAGED = [
+    # N, A, K, rows per lane, couplings: staged blocks (work split 2)
+    (16, 8, 10, 4, "j1j2"), (16, 5, 9, 2, "ring"), (20, 10, 11, 2, "a2a"),
+    (20, 7, 9, 4, "a2a"), (18, 2, 10, 1, "random"), (18, 16, 10, 2, "random"),
+    (12, 6, 9, 4, "ring"), (22, 11, 11, 1, "j1j2"), (24, 12, 10, 2, "j1j2"),
+    (9, 3, 4, 2, "j1j2"), (6, 0, 4, 4, "ring"), (6, 6, 4, 1, "ring"), (5, 1, 5, 4, "ring"),
+]
+
+
+@pytest.mark.parametrize("N,A,K,R,kind", STAGED)
+def test_staged_blocks_match_oracle_and_chunked_bitwise(N, A, K, R, kind):
+    """The staged work split gives the chunked split's result bit for bit
+    (same per-row arithmetic in the same bond order) and the oracle's."""
+    import oracle
+    print("staged blocks", N, A, K, R, kind, flush=True)
+    rng = np.random.default_rng(N * 100 + A + 7)
+    J = _J(kind, N, rng)
+    b1 = _basis(N, A, K, 256, R, 1)
+    b2 = _basis(N, A, K, 256, R, 2)
+    sub = oracle.Subspace(N, 1, A)
+    x = rng.uniform(-1, 1, sub.dim)
+    scale = _scale(sub, J, x)
+    xd = torch.tensor(x, device="cuda")
+    y2 = b2.apply(J, xd, kernel=2)
+    assert torch.equal(y2, b1.apply(J, xd, kernel=2))
+    assert np.abs(y2.cpu().numpy() - sub.apply(J, x)).max() <= 1e-13 * scale
+    x32 = xd.float()
+    y32 = b2.apply(J, x32, kernel=2)
+    assert torch.equal(y32, b1.apply(J, x32, kernel=2))
+    ref32 = sub.apply(J, x32.double().cpu().numpy())
+    assert np.abs(y32.double().cpu().numpy() - ref32).max() <= 2e-6 * scale
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
+def test_staged_blocks_lanczos_with_reorthogonalization(precision):
+    """Both fused variants of the staged kernel (with the alpha partials, and
+    with the stored Krylov vectors of full reorthogonalization): the exact
+    Majumdar-Ghosh energy, and coefficients equal to the chunked split's up to
+    the grouping of the partial sums."""
+    from paper_0706_3293_amd import inputs
+    N = 20
+    J = inputs.ring_couplings(N, -1.0, -0.5)
+    b1 = _basis(N, N // 2, 10, 256, 2, 1)
+    b2 = _basis(N, N // 2, 10, 256, 2, 2)
+    v0 = torch.tensor(inputs.start_vector(b1.dim, 0), device="cuda")
+    tol = 1e-10 if precision == "f64" else 1e-7
+    for reorth in (False, True):
+        r2 = b2.lanczos(J, v0, 120, precision=precision, full_reorth=reorth, kernel=2)
+        assert abs(r2.E0 + 3 * N / 8) <= tol * 3 * N / 8
+        r1 = b1.lanczos(J, v0, 120, precision=precision, full_reorth=reorth, kernel=2)
+        ctol = 1e-11 if precision == "f64" else 1e-5
+        assert np.abs(r1.alpha[:20] - r2.alpha[:20]).max() < ctol
+
+
+def test_staged_blocks_rejected_where_blocks_do_not_fit():
+    from paper_0706_3293_amd import _lib, inputs
+    J = inputs.ring_couplings(16, -1.0)
+    x = torch.zeros(12870, dtype=torch.float64, device="cuda")
+    for K, R in ((12, 1), (11, 4), (10, 8)):
+        b = _basis(16, 8, K, 256, R, 2)
+        with pytest.raises(_lib.HMError):
+            b.apply(J, x, kernel=2)
+    with pytest.raises(_lib.HMError):
+        _basis(16, 8, 10, 256, 1, 3)
+
+
+@pytest.mark.parametrize("N,schedule", [(28, None), (32, None), (32, (10, 256, 2, 2))])
+def test_block_kernel_full_size_sampled_rows(N, schedule):
+    """Workload sizes: sampled rows against the oracle, FP64 and FP32 (the
+    default schedule, and at N=32 the staged schedule the autotuner picks
+    for FP32 on MI355X)."""
     import oracle
     from paper_0706_3293_amd import inputs
-    print("full size", N, flush=True)
+    print("full size", N, schedule, flush=True)
     J = inputs.ring_couplings(N, -1.0, -0.5 if N == 28 else -0.25)
-    b = _basis(N, N // 2)
+    b = _basis(N, N // 2, *(schedule or ()))
     sub = oracle.Subspace(N, 1, N // 2)
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, b.dim)
@@ -101,7 +169,8 @@ def test_block_kernel_full_size_sampled_rows(N):
 
 
 @pytest.mark.parametrize("precision,schedule", [("f32_mixed", (13, 256, 8)),
-                                                ("f64", (13, 256, 4))])
+                                                ("f64", (13, 256, 4)),
+                                                ("f32_mixed", (9, 256, 4, 2))])
 def test_bench_configuration_lanczos_n28(precision, schedule):
     """The timed workload in the launch configuration the benchmark uses (the
     autotuner's schedules on MI355X): 200 steps reach the exact Majumdar-Ghosh
