@@ -59,9 +59,10 @@ def kernel_hash():
         return hashlib.sha1(f.read()).hexdigest()
 
 
-def measured_traffic(workload, prec):
+def measured_traffic(workload, prec, schedule):
     """HBM bytes per launch from the committed counter summary, or None if
-    the kernel source changed since the counters were taken."""
+    the kernel source changed since the counters were taken or they were
+    taken with another schedule."""
     try:
         with open(TRAFFIC) as f:
             t = json.load(f)
@@ -70,7 +71,9 @@ def measured_traffic(workload, prec):
     if t.get("kernel_sha1") != kernel_hash():
         return None
     e = t.get("entries", {}).get(f"{workload}/{prec}")
-    return None if e is None else e.get("bytes_per_launch")
+    if e is None or e.get("schedule") != (list(schedule) if schedule else None):
+        return None
+    return e.get("bytes_per_launch")
 
 
 def cpu_baseline(N, J, x, rows):
@@ -345,7 +348,7 @@ def main():
         else:
             t0 = time.perf_counter()
             bases[prec], schedules[prec] = autotune.tuned_basis(N, J, dtype=dt)
-            log(f"autotune {prec}: schedule (K, block, rows/lane) = {schedules[prec]} "
+            log(f"autotune {prec}: schedule (K, block, rows/lane, work split) = {schedules[prec]} "
                 f"in {time.perf_counter() - t0:.1f} s")
     D = bases["f64"].dim
     log(f"workload {args.workload} dim {D}")
@@ -375,7 +378,7 @@ def main():
         t = api.last_timing()
         avg_ms = t["hx_ms"] / max(t["hx_launches"], 1)
         alg_bytes = 3 * es * D          # read x and the previous vector, write w
-        traffic = measured_traffic(args.workload, prec)
+        traffic = measured_traffic(args.workload, prec, schedules[prec])
         hx[prec] = dict(avg_ms=avg_ms, launches=t["hx_launches"], alg_bytes=alg_bytes,
                         alg_gbs=alg_bytes / (avg_ms * 1e-3) / 1e9,
                         rows_per_s=D / (avg_ms * 1e-3), traffic_bytes=traffic,

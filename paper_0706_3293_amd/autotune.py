@@ -21,6 +21,9 @@ DEFAULT_CACHE = os.environ.get(
     "HM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hm_autotune.json"))
 
 
+TIE = 0.03      # relative timing difference treated as a tie
+
+
 def candidates(N):
     """Schedules worth trying for N sites: (K, block threads, rows per lane,
     staging), staging 1 = chunked items, 2 = staged blocks."""
@@ -82,7 +85,7 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
     x = torch.rand(probe.dim, dtype=dtype, device="cuda")
     y = torch.empty_like(x)
     del probe
-    best, best_ms, trials = None, float("inf"), []
+    trials = []
     for sched in candidates(N):
         b = Basis(N, two_s=1, two_M=two_M)
         b.set_schedule(*sched)
@@ -91,9 +94,11 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
         if verbose:
             print(f"[autotune] K={sched[0]} block={sched[1]} R={sched[2]} "
                   f"staging={sched[3]}: {ms:.3f} ms", flush=True)
-        if ms < best_ms:
-            best, best_ms = sched, ms
         del b
+    # the first candidate (in the order above) within TIE of the fastest, so
+    # that near-ties do not flip the choice from one run to the next
+    fastest = min(ms for _, ms in trials)
+    best, best_ms = next((s, ms) for s, ms in trials if ms <= (1.0 + TIE) * fastest)
     if cache:
         table[key] = {"schedule": list(best), "ms": best_ms,
                       "trials": [[list(s), m] for s, m in trials]}

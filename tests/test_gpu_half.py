@@ -168,8 +168,9 @@ def test_block_kernel_full_size_sampled_rows(N, schedule):
     assert np.abs(got32 - ref32).max() <= 2e-6 * scale
 
 
-@pytest.mark.parametrize("precision,schedule", [("f32_mixed", (13, 256, 8)),
-                                                ("f64", (13, 256, 4)),
+@pytest.mark.parametrize("precision,schedule", [("f32_mixed", (13, 256, 8, 1)),
+                                                ("f64", (13, 256, 4, 1)),
+                                                ("f64", (13, 256, 2, 1)),
                                                 ("f32_mixed", (9, 256, 4, 2))])
 def test_bench_configuration_lanczos_n28(precision, schedule):
     """The timed workload in the launch configuration the benchmark uses (the
