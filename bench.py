@@ -432,7 +432,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": h32["alg_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": h32["alg_gbs"] / HBM_PEAK_GBS,
                      "traffic": h32["traffic_bytes"],
-                     "kernel": "hx_half_kernel<float, uint32, R, DOT=true>",
+                     "kernel": ("hx_half_staged_kernel<float, uint32, R, C, DOT=true>"
+                                if (schedules["f32_mixed"] or (0, 0, 0, 1))[3] == 2
+                                else "hx_half_kernel<float, uint32, R, DOT=true>"),
+                     "schedule": schedules["f32_mixed"],
                      "alg_bytes_per_launch": h32["alg_bytes"]},
         "cpu_baseline": cpu,
         "cpu_baseline_detail": cpu_detail,
