@@ -186,7 +186,10 @@ typedef struct hm_lanczos_opts {
     int32_t full_reorth;  /* 1: classical Gram-Schmidt twice vs all v_j     */
     double breakdown_tol; /* relative; <= 0 selects 1e-12 (FP64) or 1e-6     *
                            * (FP32-mixed: the FP32 rounding floor of beta) */
-    int32_t use_graph;    /* 1: capture all steps in one hipGraph           */
+    int32_t use_graph;    /* 1: capture all steps in one hipGraph, built and
+                             instantiated anew on every call (same kernels,
+                             bitwise equal results; on MI355X the capture
+                             costs more than it saves for a single run)   */
     int32_t kernel;       /* 0: automatic choice (the one-workgroup run for
                              dim <= 2048, else the H x kernel that suits
                              the basis); 1: generic digit kernel; 2:

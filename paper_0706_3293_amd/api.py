@@ -164,7 +164,7 @@ class Basis:
         return w
 
     def lanczos(self, J, v0: torch.Tensor, steps: int, precision="f64", full_reorth=False,
-                use_graph=True, tol=0.0, kernel=0) -> LanczosResult:
+                use_graph=False, tol=0.0, kernel=0) -> LanczosResult:
         assert v0.is_cuda and v0.dtype == torch.float64 and v0.shape == (self.dim,)
         v0 = v0.contiguous()
         opts = self._opts(precision, full_reorth, use_graph, tol, kernel)
@@ -182,7 +182,7 @@ class Basis:
         return LanczosResult(alpha[:k].copy(), beta[:k].copy(), E0.value, k)
 
     def ritz(self, J, v0: torch.Tensor, steps_done: int, c, precision="f64",
-             full_reorth=False, use_graph=True, tol=0.0, kernel=0):
+             full_reorth=False, use_graph=False, tol=0.0, kernel=0):
         """psi = sum_k c_k v_k recomputed by a second identical Lanczos pass."""
         opts = self._opts(precision, full_reorth, use_graph, tol, kernel)
         work = self.workspace(steps_done, opts)

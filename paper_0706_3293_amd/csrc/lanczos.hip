@@ -63,6 +63,7 @@ struct LzDev {
     double scale;    // running max(|alpha_j|, beta_j)
     double norm0;    // |v0|
     double psi_norm;
+    unsigned ticket; // workgroups of the current fused pass B that are done
 };
 
 // One-workgroup run (below): automatic choice up to kSmallAutoDim rows,
@@ -71,7 +72,8 @@ constexpr int64_t kSmallAutoDim = 2048;
 constexpr int64_t kSmallMaxDim = 1 << 20;
 
 struct Layout {
-    size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, r0, r1, r2, V, states, total;
+    size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, bpart, r0, r1, r2, V, states,
+        total;
     int grid_vec, nparts;
 };
 
@@ -103,6 +105,7 @@ static Layout layout(const Basis *b, int steps, int prec, int reorth) {
     L.coef = off; off = align256(off + sizeof(double) * steps);
     L.hcoef = off; off = align256(off + sizeof(double) * (steps + 1));
     L.partial = off; off = align256(off + sizeof(double) * partial_len);
+    L.bpart = off; off = align256(off + sizeof(double) * kMaxGrid);
     L.r0 = off; off = align256(off + es * (size_t)b->dim);
     L.r1 = off; off = align256(off + es * (size_t)b->dim);
     L.r2 = off; off = align256(off + es * (size_t)b->dim);
@@ -155,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void finish_init(LzDev *lz, const double *p
         lz->norm0 = sqrt(s);
         lz->bad_start = !(s > 0.0);
         lz->psi_norm = 0.0;
+        lz->ticket = 0;
         sigma[0] = 1.0;
         cprev[0] = 0.0;
         if (lz->bad_start) lz->stopped = -1;
@@ -218,6 +222,71 @@ __global__ __launch_bounds__(kBlock) void finish_beta(LzDev *lz, const double *p
         } else {
             sigma[k + 1] = 1.0 / b;
             cprev[k + 1] = b * sigma[k];
+        }
+    }
+}
+
+// Pass B with the one-workgroup finishes folded in, for small grids (a few
+// dozen workgroups), where launches dominate a step.  Every workgroup sums
+// the H x partials (alpha_k) in the same fixed order, so all use the same
+// alpha, and applies w -= alpha_k sigma_k r_k.
+//   MODE 0: nothing more (reorthogonalization follows, then sumsq_kernel and
+//           finish_beta);
+//   MODE 2: each workgroup writes its |w|^2 partial to bpart and takes a
+//           device-scope ticket; the last one to arrive sums bpart in a fixed
+//           order and does what finish_beta does, then resets the ticket for
+//           the next step.
+// On large grids both cost more than they save (every workgroup re-reads all
+// H x partials, and the tickets are one contended atomic per workgroup), so
+// there the step keeps finish_alpha, pass_b and finish_beta.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void pass_b_fused(
+    T *__restrict__ w, const T *__restrict__ r, int64_t n, LzDev *lz,
+    const double *__restrict__ hx_partial, int n_hx, double *alpha, double *beta, double *sigma,
+    double *cprev, int k, double *bpart) {
+    if (lz->stopped) return;
+    __shared__ double red[16];
+    __shared__ double s_alpha;
+    __shared__ int s_last;
+    const double a_sum = fixed_sum(hx_partial, n_hx, red);
+    if (threadIdx.x == 0) {
+        s_alpha = a_sum;
+        if (blockIdx.x == 0) alpha[k] = a_sum;
+    }
+    __syncthreads();
+    const double al = s_alpha;
+    const double a = al * sigma[k];
+    int64_t first, last;
+    block_rows<int64_t>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, n, first, last);
+    double s = 0.0;
+    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+        const T wi = (T)((double)w[i] - a * (double)r[i]);
+        w[i] = wi;
+        s += (double)wi * (double)wi;
+    }
+    if constexpr (MODE == 2) {
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) {
+            bpart[blockIdx.x] = s;
+            __threadfence();                   // the partial before the ticket
+            s_last = atomicAdd(&lz->ticket, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();                       // every partial is visible
+        const double b2 = fixed_sum(bpart, gridDim.x, red);
+        if (threadIdx.x == 0) {
+            lz->ticket = 0;
+            const double b = sqrt(b2);
+            beta[k] = b;
+            const double sc = fmax(lz->scale, fmax(fabs(al), b));
+            lz->scale = sc;
+            if (!(b > lz->tol * sc)) {
+                lz->stopped = k + 1;
+            } else {
+                sigma[k + 1] = 1.0 / b;
+                cprev[k + 1] = b * sigma[k];
+            }
         }
     }
 }
@@ -309,7 +378,7 @@ __global__ void zero_f64(double *__restrict__ x, int64_t n) {
 // Small problems: the whole run in one workgroup.
 //
 // For a few thousand rows a step is little work, but the multi-kernel step
-// costs four launches (eleven with full reorthogonalization).  Here one
+// costs two launches (ten with full reorthogonalization).  Here one
 // workgroup of 1024 threads runs every step in a single launch: thread t owns
 // rows t, t + 1024, ... (the generic row of hx_row.h, on states decoded once
 // at the start and kept in the workspace), reductions are fixed
@@ -487,6 +556,9 @@ struct Run {
     double *psi;               // ritz pass output, else nullptr
 };
 
+// Largest grids (pass B and the H x partials) for the fused pass B.
+constexpr int kFusedMaxGrid = 64;
+
 template <typename T>
 static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
     Basis *b = R.b;
@@ -495,7 +567,7 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
     double *alpha = (double *)(R.w + R.L.alpha), *beta = (double *)(R.w + R.L.beta);
     double *sigma = (double *)(R.w + R.L.sigma), *cprev = (double *)(R.w + R.L.cprev);
     double *coef = (double *)(R.w + R.L.coef), *hc = (double *)(R.w + R.L.hcoef);
-    double *partial = (double *)(R.w + R.L.partial);
+    double *partial = (double *)(R.w + R.L.partial), *bpart = (double *)(R.w + R.L.bpart);
     T *buf[3] = {(T *)(R.w + R.L.r0), (T *)(R.w + R.L.r1), (T *)(R.w + R.L.r2)};
     T *V = (T *)(R.w + R.L.V);
     const int G = R.L.grid_vec;
@@ -518,22 +590,38 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
         if (R.psi)
             hipLaunchKernelGGL(psi_axpy<T>, dim3(G), dim3(kBlock), 0, R.st, R.psi, rk, n,
                                coef + k, sigma + k, lz);
-        hipLaunchKernelGGL(finish_alpha, dim3(1), dim3(kBlock), 0, R.st, lz, partial, Ghx,
-                           alpha, k);
-        hipLaunchKernelGGL(pass_b<T>, dim3(G), dim3(kBlock), 0, R.st, wn, rk, n, lz, alpha,
-                           sigma, k, partial);
-        if (R.reorth) {
-            for (int rep = 0; rep < 2; ++rep) {
-                hipLaunchKernelGGL(reorth_dots<T>, dim3(G, k + 1), dim3(kBlock), 0, R.st, V,
-                                   wn, n, k + 1, partial, lz);
-                hipLaunchKernelGGL(reorth_finish, dim3(k + 1), dim3(64), 0, R.st, partial, G,
-                                   hc, lz);
-                hipLaunchKernelGGL(reorth_update<T>, dim3(G), dim3(kBlock), 0, R.st, V, wn, n,
-                                   k + 1, hc, lz);
-            }
-            hipLaunchKernelGGL(sumsq_kernel<T>, dim3(G), dim3(kBlock), 0, R.st, wn, n, partial,
-                               &lz->stopped);
+        const bool small = G <= kFusedMaxGrid && Ghx <= kFusedMaxGrid;
+        if (small && !R.reorth) {
+            // pass B with both finishes: two launches per step in all
+            hipLaunchKernelGGL((pass_b_fused<T, 2>), dim3(G), dim3(kBlock), 0, R.st, wn, rk, n,
+                               lz, partial, Ghx, alpha, beta, sigma, cprev, k, bpart);
+            continue;
         }
+        if (small) {
+            hipLaunchKernelGGL((pass_b_fused<T, 0>), dim3(G), dim3(kBlock), 0, R.st, wn, rk, n,
+                               lz, partial, Ghx, alpha, beta, sigma, cprev, k, bpart);
+        } else {
+            hipLaunchKernelGGL(finish_alpha, dim3(1), dim3(kBlock), 0, R.st, lz, partial, Ghx,
+                               alpha, k);
+            hipLaunchKernelGGL(pass_b<T>, dim3(G), dim3(kBlock), 0, R.st, wn, rk, n, lz, alpha,
+                               sigma, k, partial);
+        }
+        if (!R.reorth) {
+            hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G,
+                               alpha, beta, sigma, cprev, k);
+            continue;
+        }
+        // with full reorthogonalization beta is the norm after it
+        for (int rep = 0; rep < 2; ++rep) {
+            hipLaunchKernelGGL(reorth_dots<T>, dim3(G, k + 1), dim3(kBlock), 0, R.st, V, wn, n,
+                               k + 1, partial, lz);
+            hipLaunchKernelGGL(reorth_finish, dim3(k + 1), dim3(64), 0, R.st, partial, G, hc,
+                               lz);
+            hipLaunchKernelGGL(reorth_update<T>, dim3(G), dim3(kBlock), 0, R.st, V, wn, n,
+                               k + 1, hc, lz);
+        }
+        hipLaunchKernelGGL(sumsq_kernel<T>, dim3(G), dim3(kBlock), 0, R.st, wn, n, partial,
+                           &lz->stopped);
         hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G, alpha,
                            beta, sigma, cprev, k);
     }

@@ -337,3 +337,24 @@ def test_one_workgroup_run_size_limit():
     v0 = torch.ones(b.dim, dtype=torch.float64, device="cuda")
     with pytest.raises(_lib.HMError):
         b.lanczos(inputs.ring_couplings(24, -1.0), v0, 2, kernel=3)
+
+
+@pytest.mark.parametrize("N,kernel,reorth", [(20, 2, False), (20, 1, False), (10, 1, False),
+                                             (12, 1, True), (20, 2, True)])
+def test_graph_and_eager_runs_are_bitwise_equal(N, kernel, reorth):
+    """A run captured in one hipGraph launches the same kernels as the eager
+    run, so the coefficients agree bit for bit: large grids (finish kernels),
+    small grids (pass B with the last-workgroup finish), with and without
+    reorthogonalization."""
+    from paper_0706_3293_amd import inputs
+    b = _basis(N, 1, N // 2)
+    J = inputs.ring_couplings(N, -1.0, -0.5)
+    v0 = torch.tensor(inputs.start_vector(b.dim, 3), device="cuda")
+    for precision in ("f64", "f32_mixed"):
+        r0 = b.lanczos(J, v0, 60, precision=precision, full_reorth=reorth, use_graph=False,
+                       kernel=kernel)
+        for _ in range(2):
+            r1 = b.lanczos(J, v0, 60, precision=precision, full_reorth=reorth, use_graph=True,
+                           kernel=kernel)
+            assert r1.steps_done == r0.steps_done
+            assert np.array_equal(r1.alpha, r0.alpha) and np.array_equal(r1.beta, r0.beta)
