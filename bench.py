@@ -177,9 +177,12 @@ def extras():
     # multi-kernel step captured in one graph
     for name, kern in (("one_workgroup", 0), ("multi_kernel", 1)):
         b.lanczos(J, v0, 120, full_reorth=True, kernel=kern)
-        t0 = time.perf_counter()
-        res = b.lanczos(J, v0, 120, full_reorth=True, kernel=kern)
-        out["ring12"][name + "_ms"] = 1e3 * (time.perf_counter() - t0)
+        best = float("inf")
+        for _ in range(3):                      # best of three (short run)
+            t0 = time.perf_counter()
+            res = b.lanczos(J, v0, 120, full_reorth=True, kernel=kern)
+            best = min(best, time.perf_counter() - t0)
+        out["ring12"][name + "_ms"] = 1e3 * best
         out["ring12"][name + "_E0"] = res.E0
     # N=20 all-to-all: E0(J) forward (300 steps FP64) and gradient of 190 bonds
     b = Basis(20, two_s=1, two_M=0)
@@ -283,9 +286,11 @@ def extras():
     v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
     b.lanczos(Jp, v0, 200)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = b.lanczos(Jp, v0, 200)
-    dt = time.perf_counter() - t0
+    dt = float("inf")
+    for _ in range(3):                          # best of three (short run)
+        t0 = time.perf_counter()
+        res = b.lanczos(Jp, v0, 200)
+        dt = min(dt, time.perf_counter() - t0)
     out["paper_vector_length_484500"] = dict(ms=1e3 * dt, dim=b.dim, steps=200,
                                              ms_per_step=1e3 * dt / 200, E0=res.E0)
     # the largest size: N=36 J1-J2 ring at M=0 (dim 9,075,135,300 > 2^32, 64-bit
