@@ -173,9 +173,9 @@ def extras():
     J = inputs.ring_couplings(12, -1.0)
     v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
     out["ring12"] = dict(steps=120)
-    # kernel 0 picks the one-workgroup run at this size; kernel 1 is the
-    # multi-kernel step captured in one graph
-    for name, kern in (("one_workgroup", 0), ("multi_kernel", 1)):
+    # kernel 3: every step in one launch of one workgroup; kernel 1: the
+    # multi-kernel step (what the automatic choice runs with reorthogonalization)
+    for name, kern in (("one_workgroup", 3), ("multi_kernel", 1)):
         b.lanczos(J, v0, 120, full_reorth=True, kernel=kern)
         best = float("inf")
         for _ in range(3):                      # best of three (short run)
@@ -196,8 +196,12 @@ def extras():
     t1 = time.perf_counter()
     E0.backward()
     t2 = time.perf_counter()
+    # bond evaluations: every row tests every bond once per H x (300 forward
+    # steps; the backward repeats them and adds one pass over all bonds)
+    bond_evals = 300 * b.dim * len(bonds)
     out["all_to_all20"] = dict(forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1),
                                steps=300, bonds=len(bonds), E0=float(E0.detach()),
+                               forward_bond_evals_per_s=bond_evals / (t1 - t0),
                                euler_residual=abs(float(np.dot(vals, Jv.grad.numpy())) - float(E0)))
     # 64 spin-1 chains x 16 start vectors x 80 steps, one persistent launch
     inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)

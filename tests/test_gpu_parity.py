@@ -171,8 +171,10 @@ def _golden(name):
         return json.load(f)
 
 
-# Lanczos paths: kernel 0 picks the one-workgroup run at these sizes, kernel 1
-# forces the multi-kernel step (generic H x), kernel 3 the one-workgroup run.
+# Lanczos paths: kernel 0 is the automatic choice (at these sizes the
+# one-workgroup run without reorthogonalization, the block kernel's
+# multi-kernel step with it), kernel 1 forces the multi-kernel step with the
+# generic H x, kernel 3 the one-workgroup run.
 @pytest.mark.parametrize("use_graph,kernel", [(False, 1), (True, 1), (True, 0), (False, 3)])
 def test_lanczos_ring12_matches_oracle(use_graph, kernel):
     """N=12 ring, 120 steps with full reorthogonalization, FP64."""
