@@ -268,12 +268,15 @@ __global__ __launch_bounds__(kBlock) void pass_b_fused(
         s = block_sum(s, red);
         if (threadIdx.x == 0) {
             bpart[blockIdx.x] = s;
-            __threadfence();                   // the partial before the ticket
-            s_last = atomicAdd(&lz->ticket, 1u) == gridDim.x - 1;
+            // the release orders the partial before the ticket; the last
+            // workgroup acquires every partial before summing them
+            const unsigned t = __hip_atomic_fetch_add(&lz->ticket, 1u, __ATOMIC_RELEASE,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            s_last = t == gridDim.x - 1;
+            if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
         if (!s_last) return;
-        __threadfence();                       // every partial is visible
         const double b2 = fixed_sum(bpart, gridDim.x, red);
         if (threadIdx.x == 0) {
             lz->ticket = 0;
