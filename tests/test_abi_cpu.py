@@ -93,6 +93,19 @@ def test_error_paths(L):
         b.rank([3, 0, 0, 0, 0, 3])            # digit > 2s
     with pytest.raises(_lib.HMError):
         b.rank([1, 0, 0, 0, 0, 0])            # wrong digit sum
+    # schedule and work-split arguments are checked on the host
+    h = Basis(16, two_s=1, two_M=0)
+    for args in ((15, 0, 0), (0, 96, 0), (0, 0, 3), (9, 0, 0)):
+        if args == (9, 0, 0):
+            h.set_schedule(*args)                # valid: K = 9
+            continue
+        with pytest.raises(_lib.HMError):
+            h.set_schedule(*args)
+    for mode in (-1, 3):
+        assert L.hm_basis_set_staging(h.handle, mode) == _lib.HM_EINVAL
+    assert L.hm_basis_set_staging(None, 1) == _lib.HM_EINVAL
+    for mode in (0, 1, 2):
+        assert L.hm_basis_set_staging(h.handle, mode) == _lib.HM_OK
     out = ctypes.c_int64()
     assert L.hm_count(3, 0, 0, ctypes.byref(out)) == _lib.HM_EINVAL
     assert L.hm_count(3, 1, 0, None) == _lib.HM_EINVAL
