@@ -190,9 +190,9 @@ typedef struct hm_lanczos_opts {
                              instantiated anew on every call (same kernels,
                              bitwise equal results; on MI355X the capture
                              costs more than it saves for a single run)   */
-    int32_t kernel;       /* 0: automatic choice (the one-workgroup run for
-                             dim <= 2048 without full_reorth, else the H x
-                             kernel that suits
+    int32_t kernel;       /* 0: automatic choice (the one-workgroup run
+                             without full_reorth when dim x bonds <=
+                             16384, else the H x kernel that suits
                              the basis); 1: generic digit kernel; 2:
                              spin-1/2 block kernel (if the basis is spin
                              1/2); 3: one-workgroup run (every step in one

@@ -66,9 +66,10 @@ struct LzDev {
     unsigned ticket; // workgroups of the current fused pass B that are done
 };
 
-// One-workgroup run (below): automatic choice up to kSmallAutoDim rows without
-// reorthogonalization, accepted when asked for explicitly up to kSmallMaxDim.
-constexpr int64_t kSmallAutoDim = 2048;
+// One-workgroup run (below): automatic choice without reorthogonalization up
+// to kSmallAutoWork (rows x bonds) of row work per step, accepted when asked
+// for explicitly up to kSmallMaxDim rows.
+constexpr int64_t kSmallAutoWork = 16384;
 constexpr int64_t kSmallMaxDim = 1 << 20;
 
 struct Layout {
@@ -389,12 +390,13 @@ __global__ void zero_f64(double *__restrict__ x, int64_t n) {
 // run is reproducible and the recompute pass repeats it bit for bit.  The
 // recurrence is the same (Paige's ordering, the same breakdown test); v_k is
 // stored normalized.  One compute unit does all the row work, so the run pays
-// off only while that work stays below the launch costs it saves: measured
-// against directly launched steps, it is faster up to about 1000-2000 rows
-// without reorthogonalization (0.46 vs 0.65 ms for 60 steps at 70 rows, 1.4
-// vs 1.7 ms for 120 steps at 924 rows) and slower at 3432 rows (5.2 vs
-// 2.7 ms); with reorthogonalization, whose k-term sums run on this one
-// workgroup, it is slower already at 924 rows (7.7 vs 5.3 ms).
+// off only while that work stays below the launch costs it saves.  Measured
+// against directly launched steps, without reorthogonalization: faster at 70
+// rows x 8 bonds (0.46 vs 0.65 ms, 60 steps), 924 x 12 (1.4 vs 1.7 ms, 120
+// steps) and 1107 x 7 (1.2 vs 1.7 ms, 100 steps); slower at 3432 x 14 (5.2
+// vs 2.7 ms, 150 steps) and 2024 x 48 (5.4 ms, 150 steps).  With
+// reorthogonalization, whose k-term sums run on this one workgroup, it is
+// slower already at 924 rows (7.7 vs 5.3 ms).
 // ---------------------------------------------------------------------------
 constexpr int kSmallBlock = 1024;
 
@@ -818,7 +820,7 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     const Couplings *c = nullptr;
     HM_TRY(get_couplings(b, J, &c));
     const bool small = o->kernel == 3 || (o->kernel == 0 && !g_timing && !o->full_reorth &&
-                                          b->dim <= kSmallAutoDim);
+                                          b->dim * (int64_t)std::max(c->nb, 1) <= kSmallAutoWork);
     const int kernel = small ? 1 : choose_kernel(b, c, o->kernel);
     if (kernel < 0) return fail(HM_ERANGE, "block kernel tables too large for these couplings");
     if (kernel == 2) HM_TRY(half_prepare_tables(b, c));
