@@ -174,6 +174,60 @@ __device__ __forceinline__ void item_partials(double (&v)[NV], double *stage, do
     __syncthreads();
 }
 
+// Lanes per row in the two row passes: with 8 or 16 vectors a row is split
+// over NV/4 lanes of 4 vectors (16 bytes) each, so the lanes of a wave read
+// whole 64-byte rows together (a 64-lane load touches 16 lines, not 64).  The
+// lanes of a row share its bond work (each takes every G-th bond of a batch)
+// and pass the targets and coefficients around with quad permutes.
+template <int NV>
+constexpr int lanes_per_row() { return NV >= 8 ? NV / 4 : 1; }
+
+// Value of lane t of this lane's group of G consecutive lanes (G = 2 or 4;
+// groups never straddle a quad), by a DPP quad permute.
+template <int G>
+__device__ __forceinline__ uint32_t group_lane(uint32_t v, int t) {
+    if constexpr (G == 4) {
+        switch (t) {   // quad_perm [t, t, t, t]
+            case 0: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x00, 0xf, 0xf, false);
+            case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x55, 0xf, 0xf, false);
+            case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xaa, 0xf, 0xf, false);
+            default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xff, 0xf, 0xf, false);
+        }
+    } else {
+        switch (t) {   // quad_perm [t, t, 2 + t, 2 + t]
+            case 0: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xa0, 0xf, 0xf, false);
+            default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xf5, 0xf, 0xf, false);
+        }
+    }
+}
+
+// item_partials when G lanes share a row: lane l holds the V = NV / G columns
+// starting at (l % G) V.  A fixed butterfly over the lanes of one column group
+// (offsets 32 down to G), then thread q < NV adds the wave sums of column q in
+// wave order.  G = 1 is item_partials.
+template <int NV, int G>
+__device__ __forceinline__ void item_partials_g(double (&v)[NV / G], double *stage,
+                                                double *out) {
+    constexpr int V = NV / G;
+#pragma unroll
+    for (int off = 32; off >= G; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane < G) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) stage[wid * NV + lane * V + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += stage[w * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // Sum of column q of the item partials [first, first + count): lane l adds
 // items l, l + 64, ... in order, then a fixed butterfly over the lanes.  Every
 // lane of the wave returns the same value.
@@ -281,15 +335,18 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
     }
     if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
 
+    // row passes: G lanes per row, this lane's V columns start at gq
+    constexpr int G = lanes_per_row<NV>(), V = NV / G;
+    const int gl = (int)(threadIdx.x % G), gq = gl * V;
     int loaded = -1;   // instance whose tables are in LDS
     for (int k = 0; k < a.steps; ++k) {
         const float *__restrict__ rk = a.r[k % 3];
         const float *__restrict__ rp = a.r[(k + 2) % 3];
         float *__restrict__ w = a.r[(k + 1) % 3];
         // ---- A: w = sigma H r_k - cprev r_{k-1}; alpha partials ----------
-        double dacc[NV];
+        double dacc[V];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) dacc[q] = 0.0;
+        for (int q = 0; q < V; ++q) dacc[q] = 0.0;
         int sc_loaded = -1;
         for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
             const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
@@ -335,28 +392,40 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
                 const uint32_t vec_off = __builtin_amdgcn_readfirstlane(s_vec_off);
                 const uint32_t item_end = __builtin_amdgcn_readfirstlane(s_item_end);
                 const Prefix<uint32_t> pv{P, iA + 1, two_s + 1};
-                const uint32_t i = itm.row0 + threadIdx.x;
-                if (i < dim) {
-                    const float *__restrict__ xr = rk + (size_t)vec_off * NV;
-                    const uint64_t st = unrank_state<uint32_t, B>(i, pv, iN, iA, two_s);
-                    float xi[NV], acc[NV];
-                    load_row<NV>(xr + (size_t)i * NV, xi);
+                const float *__restrict__ xr = rk + (size_t)vec_off * NV;
+                // lane gl of a group decodes the group's row of sub-iteration gl,
+                // so each row is decoded once; the state is passed around below
+                const uint32_t i_mine = itm.row0 + gl * (kBatchBlock / G) + threadIdx.x / G;
+                const uint64_t st_mine =
+                    i_mine < dim ? unrank_state<uint32_t, B>(i_mine, pv, iN, iA, two_s) : 0;
+                for (int sub = 0; sub < G; ++sub) {
+                    const uint32_t i = itm.row0 + sub * (kBatchBlock / G) + threadIdx.x / G;
+                    if (i >= dim) continue;   // the G lanes of a row leave together
+                    uint64_t st = st_mine;
+                    if constexpr (G > 1)
+                        st = (uint64_t)group_lane<G>((uint32_t)st_mine, sub) |
+                             ((uint64_t)group_lane<G>((uint32_t)(st_mine >> 32), sub) << 32);
+                    float xi[V], acc[V];
+                    load_row<V>(xr + (size_t)i * NV + gq, xi);
     #pragma unroll
-                    for (int q = 0; q < NV; ++q) acc[q] = 0.0f;
+                    for (int q = 0; q < V; ++q) acc[q] = 0.0f;
                     float diag = 0.0f;
                     // moves in batches: targets and coefficients first (a move that
                     // is not allowed reads the own row with coefficient 0), then all
-                    // row loads of the batch, then the products, so kMoves row
-                    // gathers are in flight together
-                    constexpr int kMoves = NV >= 16 ? 4 : (NV >= 8 ? 8 : 16);
+                    // row loads of the batch, then the products in bond order, so
+                    // kMoves row gathers are in flight together.  With G > 1 lane
+                    // gl of a row finds the moves of bonds gl*BPL .. gl*BPL+BPL-1
+                    // of the batch and the group shares them.
+                    constexpr int kMoves = G > 1 ? 8 : 16;
+                    constexpr int BPL = kMoves / 2 / G;      // bonds per lane and batch
                     for (int b0 = 0; b0 < nb; b0 += kMoves / 2) {
-                        uint32_t jm[kMoves];
-                        float cm[kMoves];
+                        uint32_t jo[2 * BPL];
+                        float co[2 * BPL];
     #pragma unroll
-                        for (int t = 0; t < kMoves / 2; ++t) {
-                            jm[2 * t] = jm[2 * t + 1] = i;
-                            cm[2 * t] = cm[2 * t + 1] = 0.0f;
-                            const int b = b0 + t;
+                        for (int t = 0; t < BPL; ++t) {
+                            jo[2 * t] = jo[2 * t + 1] = i;
+                            co[2 * t] = co[2 * t + 1] = 0.0f;
+                            const int b = b0 + gl * BPL + t;
                             if (b < nb) {
                                 const LdsBond bd = Bd[b];
                                 const int u = bd.uv & 0xffff, v = bd.uv >> 16;
@@ -364,40 +433,69 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
                                 const int au = digit_at<B>(st, u), av = digit_at<B>(st, v);
                                 diag += bd.mJ4 * (float)((two_s - 2 * au) * (two_s - 2 * av));
                                 if (au >= 1 && av < two_s) {
-                                    jm[2 * t] = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
-                                    cm[2 * t] = (float)(mJ2 * F[au] * F[av + 1]);
+                                    jo[2 * t] = i + move_delta<uint32_t, B>(st, u, v, -1, pv);
+                                    co[2 * t] = (float)(mJ2 * F[au] * F[av + 1]);
                                 }
                                 if (av >= 1 && au < two_s) {
-                                    jm[2 * t + 1] = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
-                                    cm[2 * t + 1] = (float)(mJ2 * F[av] * F[au + 1]);
+                                    jo[2 * t + 1] = i + move_delta<uint32_t, B>(st, u, v, +1, pv);
+                                    co[2 * t + 1] = (float)(mJ2 * F[av] * F[au + 1]);
                                 }
                             }
                         }
-                        float xj[kMoves][NV];
+                        uint32_t jm[kMoves];
+                        float cm[kMoves];
+                        if constexpr (G == 1) {
     #pragma unroll
-                        for (int m = 0; m < kMoves; ++m) load_row<NV>(xr + (size_t)jm[m] * NV, xj[m]);
+                            for (int m = 0; m < kMoves; ++m) {
+                                jm[m] = jo[m];
+                                cm[m] = co[m];
+                            }
+                        } else {
+    #pragma unroll
+                            for (int src = 0; src < G; ++src)
+    #pragma unroll
+                                for (int m = 0; m < 2 * BPL; ++m) {
+                                    jm[src * 2 * BPL + m] = group_lane<G>(jo[m], src);
+                                    cm[src * 2 * BPL + m] = __uint_as_float(
+                                        group_lane<G>(__float_as_uint(co[m]), src));
+                                }
+                        }
+                        float xj[kMoves][V];
+    #pragma unroll
+                        for (int m = 0; m < kMoves; ++m)
+                            load_row<V>(xr + (size_t)jm[m] * NV + gq, xj[m]);
     #pragma unroll
                         for (int m = 0; m < kMoves; ++m)
     #pragma unroll
-                            for (int q = 0; q < NV; ++q) acc[q] += cm[m] * xj[m][q];
+                            for (int q = 0; q < V; ++q) acc[q] += cm[m] * xj[m][q];
                     }
-                    float prv[NV];
-                    if (k > 0) load_row<NV>(rp + ((size_t)vec_off + i) * NV, prv);
-                    float out[NV];
+                    if constexpr (G > 1) {
+                        // the diagonal: each lane summed its own bonds; add the
+                        // group's parts in lane order (same value in every lane)
+                        const uint32_t db = __float_as_uint(diag);
+                        float dsum = 0.0f;
     #pragma unroll
-                    for (int q = 0; q < NV; ++q) {
-                        const double hv = (double)(diag * xi[q] + acc[q]);
-                        double wq = sc_sigma[q] * hv;
-                        if (k > 0) wq -= sc_c[q] * (double)prv[q];
-                        out[q] = (float)wq;
-                        dacc[q] += (double)out[q] * (sc_sigma[q] * (double)xi[q]);
+                        for (int src = 0; src < G; ++src)
+                            dsum += __uint_as_float(group_lane<G>(db, src));
+                        diag = dsum;
                     }
-                    store_row<NV>(w + ((size_t)vec_off + i) * NV, out);
+                    float prv[V];
+                    if (k > 0) load_row<V>(rp + ((size_t)vec_off + i) * NV + gq, prv);
+                    float out[V];
+    #pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const double hv = (double)(diag * xi[q] + acc[q]);
+                        double wq = sc_sigma[gq + q] * hv;
+                        if (k > 0) wq -= sc_c[gq + q] * (double)prv[q];
+                        out[q] = (float)wq;
+                        dacc[q] += (double)out[q] * (sc_sigma[gq + q] * (double)xi[q]);
+                    }
+                    store_row<V>(w + ((size_t)vec_off + i) * NV + gq, out);
                 }
                 if (it + 1 == i1 || (uint32_t)(it + 1) == item_end) {
-                    item_partials<NV>(dacc, stage, a.partial + (size_t)seg * NV);
+                    item_partials_g<NV, G>(dacc, stage, a.partial + (size_t)seg * NV);
     #pragma unroll
-                    for (int q = 0; q < NV; ++q) dacc[q] = 0.0;
+                    for (int q = 0; q < V; ++q) dacc[q] = 0.0;
                     seg = it + 1;
                 }
             }
@@ -411,9 +509,9 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
         }
         if (!grid_barrier(a.bar, nblocks, &ok_flag)) return;
         // ---- B: w -= alpha sigma r_k; |w|^2 partials -----------------------
-        double ss[NV];
+        double ss[V];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) ss[q] = 0.0;
+        for (int q = 0; q < V; ++q) ss[q] = 0.0;
         sc_loaded = -1;
         for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
             const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
@@ -438,23 +536,24 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
                 const uint32_t dim = __builtin_amdgcn_readfirstlane(sb_dim);
                 const uint32_t vec_off = __builtin_amdgcn_readfirstlane(sb_vec_off);
                 const uint32_t item_end = __builtin_amdgcn_readfirstlane(sb_item_end);
-                const uint32_t i = itm.row0 + threadIdx.x;
-                if (i < dim) {
-                    const size_t row = ((size_t)vec_off + i) * NV;
-                    float wv[NV], rv[NV];
-                    load_row<NV>(w + row, wv);
-                    load_row<NV>(rk + row, rv);
+                for (int sub = 0; sub < G; ++sub) {
+                    const uint32_t i = itm.row0 + sub * (kBatchBlock / G) + threadIdx.x / G;
+                    if (i >= dim) continue;
+                    const size_t row = ((size_t)vec_off + i) * NV + gq;
+                    float wv[V], rv[V];
+                    load_row<V>(w + row, wv);
+                    load_row<V>(rk + row, rv);
     #pragma unroll
-                    for (int q = 0; q < NV; ++q) {
-                        wv[q] = (float)((double)wv[q] - sc_a[q] * (double)rv[q]);
+                    for (int q = 0; q < V; ++q) {
+                        wv[q] = (float)((double)wv[q] - sc_a[gq + q] * (double)rv[q]);
                         ss[q] += (double)wv[q] * (double)wv[q];
                     }
-                    store_row<NV>(w + row, wv);
+                    store_row<V>(w + row, wv);
                 }
                 if (it + 1 == i1 || (uint32_t)(it + 1) == item_end) {
-                    item_partials<NV>(ss, stage, a.partial + (size_t)seg * NV);
+                    item_partials_g<NV, G>(ss, stage, a.partial + (size_t)seg * NV);
     #pragma unroll
-                    for (int q = 0; q < NV; ++q) ss[q] = 0.0;
+                    for (int q = 0; q < V; ++q) ss[q] = 0.0;
                     seg = it + 1;
                 }
             }
