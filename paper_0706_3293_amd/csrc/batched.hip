@@ -4,7 +4,8 @@
 // Vectors are stored in FP32 as [dim][NV] rows (NV = 1, 2, 4, 8 or 16), so the
 // multi-vector product H X decodes each basis state and encodes each target
 // once (Sec. 3.1, 3.2) and gathers the NV entries of a target row with
-// contiguous 16-byte loads.  Dots and norms are FP64.  Each (instance,
+// contiguous 16-byte loads; with 8 or 16 vectors a row is spread over 2 or 4
+// lanes, which share its decoding and bond work.  Dots and norms are FP64.  Each (instance,
 // vector) pair runs its own recurrence (Paige's ordering, as hm_lanczos):
 //
 //   init  norms of the start vectors, r_0 = v0 / |v0|            (2 barriers)
