@@ -13,7 +13,7 @@
 
 namespace hm {
 
-template <typename T, typename I, int B, bool DOT, bool STORE>
+template <typename T, typename I, int B, bool DOT, bool STORE, bool TAB>
 __global__ __launch_bounds__(kBlock) void hx_generic_kernel(
     const I *__restrict__ gprefix, const double *__restrict__ gladder,
     const BondDev *__restrict__ bonds, int nb, int N, int A, int two_s, I dim,
@@ -25,7 +25,11 @@ __global__ __launch_bounds__(kBlock) void hx_generic_kernel(
     __shared__ double red[16];
     const int plen = N * (A + 1) * (two_s + 1);
     I *P = reinterpret_cast<I *>(smem);
-    T *F = reinterpret_cast<T *>(smem + ((plen * sizeof(I) + 15) / 16) * 16);
+    const size_t pbytes = ((plen * sizeof(I) + 15) / 16) * 16;
+    T *F = reinterpret_cast<T *>(smem + pbytes);
+    // TAB: this lane's column of the per-site term positions (row_hx_tab)
+    const size_t fbytes = (((size_t)two_s + 2) * sizeof(double) + 15) / 16 * 16;
+    uint16_t *sb = reinterpret_cast<uint16_t *>(smem + pbytes + fbytes) + threadIdx.x;
     for (int t = threadIdx.x; t < plen; t += blockDim.x) P[t] = gprefix[t];
     for (int t = threadIdx.x; t < two_s + 2; t += blockDim.x) F[t] = (T)gladder[t];
     __syncthreads();
@@ -40,7 +44,11 @@ __global__ __launch_bounds__(kBlock) void hx_generic_kernel(
     for (I row = first + threadIdx.x; row < last; row += blockDim.x) {
         const uint64_t st = unrank_state<I, B>(row, pv, N, A, two_s);
         const T xi = x[row];
-        const T hv = row_hx<T, I, B>(st, row, xi, x, bonds, nb, two_s, pv, F);
+        T hv;
+        if constexpr (TAB)
+            hv = row_hx_tab<T, I, B>(st, row, xi, x, bonds, nb, N, two_s, pv, F, sb, blockDim.x);
+        else
+            hv = row_hx<T, I, B>(st, row, xi, x, bonds, nb, two_s, pv, F);
         double w = sigma * (double)hv;
         if (prev) w -= cprev * (double)prev[row];
         const T wt = (T)w;
@@ -122,6 +130,9 @@ int generic_grid(int64_t rows) {
 
 int hx_generic_grid(const Basis *b) { return generic_grid(b->dim); }
 
+// LDS a workgroup of the generic kernel may take with the term positions.
+constexpr size_t kMaxGenericLds = 64 * 1024;
+
 template <typename T, typename I, int B>
 static void launch_hx_t(const Basis *b, const Couplings *c, const HxPass &p, int grid,
                         size_t lds, hipStream_t st) {
@@ -131,14 +142,29 @@ static void launch_hx_t(const Basis *b, const Couplings *c, const HxPass &p, int
     const T *pr = (const T *)p.p;
     T *store = (T *)p.store;
     const bool dot = p.partial != nullptr, sto = store != nullptr;
-#define HM_LAUNCH(D, S)                                                                   \
-    hipLaunchKernelGGL((hx_generic_kernel<T, I, B, D, S>), dim3(grid), dim3(kBlock), lds, \
-                       st, pref, b->d_ladder, c->dev, c->nb, b->N, b->A, b->two_s,        \
-                       (I)b->dim, x, y, pr, p.sigma, p.cprev, p.partial, store, p.stopped)
-    if (!dot && !sto) HM_LAUNCH(false, false);
-    else if (dot && !sto) HM_LAUNCH(true, false);
-    else if (!dot && sto) HM_LAUNCH(false, true);
-    else HM_LAUNCH(true, true);
+    // tabulated term positions (row_hx_tab) for s >= 1: N x 256 x 2 bytes of
+    // LDS beside the prefix table, and positions that fit 16 bits.  Measured
+    // (one FP32 H x): s = 1, N = 16 ring 0.284 -> 0.268 ms; s = 2, N = 12
+    // ring 0.924 -> 0.826 ms; for s = 1/2 it was slower (N = 28 J1-J2 ring
+    // 4.56 -> 5.04 ms), where the digit walks are single popcounts.
+    const size_t lds_tab = lds + (size_t)b->N * kBlock * sizeof(uint16_t);
+    const bool tab = b->two_s >= 2 && lds_tab <= kMaxGenericLds && b->prefix_len() <= 65535;
+#define HM_LAUNCH(D, S, TB)                                                                 \
+    hipLaunchKernelGGL((hx_generic_kernel<T, I, B, D, S, TB>), dim3(grid), dim3(kBlock),    \
+                       TB ? lds_tab : lds, st, pref, b->d_ladder, c->dev, c->nb, b->N, b->A, \
+                       b->two_s, (I)b->dim, x, y, pr, p.sigma, p.cprev, p.partial, store,  \
+                       p.stopped)
+    if (tab) {
+        if (!dot && !sto) HM_LAUNCH(false, false, true);
+        else if (dot && !sto) HM_LAUNCH(true, false, true);
+        else if (!dot && sto) HM_LAUNCH(false, true, true);
+        else HM_LAUNCH(true, true, true);
+    } else {
+        if (!dot && !sto) HM_LAUNCH(false, false, false);
+        else if (dot && !sto) HM_LAUNCH(true, false, false);
+        else if (!dot && sto) HM_LAUNCH(false, true, false);
+        else HM_LAUNCH(true, true, false);
+    }
 #undef HM_LAUNCH
 }
 
@@ -163,7 +189,9 @@ int launch_hx_generic(const Basis *b, const Couplings *c, int dtype, const HxPas
                       hipStream_t st) {
     HM_TRY(check_lds(b));
     const int grid = generic_grid(b->dim);
-    const size_t lds = ((prefix_bytes(b) + 15) / 16) * 16 + (b->two_s + 2) * sizeof(double);
+    // prefix table, then the 2s + 2 ladder factors (room for doubles)
+    const size_t lds = ((prefix_bytes(b) + 15) / 16) * 16 +
+                       (((size_t)b->two_s + 2) * sizeof(double) + 15) / 16 * 16;
     int rc;
     if (dtype == HM_F64)
         rc = b->idx32 ? dispatch_bits<double, uint32_t>(b, c, p, grid, lds, st)
