@@ -23,13 +23,16 @@ def _rand_J(N, rng):
     return J + J.T
 
 
-def test_batched_heterogeneous_spin_half_vs_single_and_oracle():
+@pytest.mark.parametrize("nvec", [3, 7, 12])
+def test_batched_heterogeneous_spin_half_vs_single_and_oracle(nvec):
+    """nvec 3, 7, 12 run 4, 8 and 16 columns: one lane per row, and rows
+    shared by 2 and 4 lanes."""
     import oracle
     from paper_0706_3293_amd import Basis, lanczos_batched
-    rng = np.random.default_rng(0)
+    print("batched vs single and oracle, nvec", nvec, flush=True)
+    rng = np.random.default_rng(nvec)
     specs = [(8, 4), (10, 5), (12, 6), (10, 3), (14, 7), (6, 3), (9, 4)]
     bases, Js, V0s = [], [], []
-    nvec = 3
     for N, A in specs:
         b = Basis(N, two_s=1, two_M=N - 2 * A)
         bases.append(b)
@@ -104,3 +107,30 @@ def test_batched_full_workload_runs():
     assert np.all(np.isfinite(res.E0))
     for k in range(64):
         assert np.ptp(res.E0[k]) <= 1e-4 * abs(res.E0[k].mean())
+
+
+@pytest.mark.parametrize("nvec", [8, 16])
+def test_batched_spin_one_and_three_halves_vs_oracle(nvec):
+    """General spin in the shared-row layout: s = 1 and s = 3/2 chains with
+    8 and 16 columns against the oracle's FP64 recurrence."""
+    import oracle
+    from paper_0706_3293_amd import Basis, lanczos_batched
+    rng = np.random.default_rng(100 + nvec)
+    # one launch per spin (the instances of a launch share it); (N, 2s, A)
+    for specs in ([(8, 2, 8), (7, 2, 5), (9, 2, 7)], [(6, 3, 9), (5, 3, 6)]):
+        bases, Js, V0s = [], [], []
+        for N, two_s, A in specs:
+            b = Basis(N, two_s=two_s, two_M=N * two_s - 2 * A)
+            bases.append(b)
+            Js.append(_rand_J(N, rng))
+            V0s.append(rng.uniform(-1, 1, (nvec, b.dim)))
+        steps = 30
+        res = lanczos_batched(bases, Js, V0s, steps)
+        for k, (N, two_s, A) in enumerate(specs):
+            sub = oracle.Subspace(N, two_s, A)
+            for r in range(nvec):
+                ref = oracle.lanczos(sub, Js[k], V0s[k][r], steps)
+                assert res.steps_done[k, r] == ref["steps_done"], (k, r)
+                assert np.abs(res.alpha[k, r, :5] - ref["alpha"][:5]).max() <= \
+                    2e-6 * np.abs(ref["alpha"][:5]).max()
+                assert abs(res.E0[k, r] - ref["E0"]) <= 1e-6 * abs(ref["E0"])
