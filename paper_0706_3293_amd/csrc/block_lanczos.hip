@@ -124,6 +124,60 @@ __global__ __launch_bounds__(kDotBlock) void block_dots_kernel(const double *__r
     }
 }
 
+// The same dots for P <= 4, JC blocks per workgroup: a thread keeps the P
+// entries of W of its row in registers and adds the outer products with the
+// rows of JC consecutive blocks, so each entry of W and X_j is loaded once per
+// chunk (the kernel above loads each P times and W once per block).  Sums
+// in a fixed order: per thread over its rows, a butterfly per wave, the waves
+// in order.
+constexpr int kDotChunk = 4;
+
+template <int P>
+__global__ __launch_bounds__(kDotBlock) void block_dots_chunk_kernel(
+    const double *__restrict__ X, const double *__restrict__ W, int64_t dim, int nblk,
+    double *__restrict__ partial) {
+    constexpr int PP = P * P, JC = kDotChunk;
+    __shared__ double stage[(kDotBlock / 64) * JC * PP];
+    const int j0 = blockIdx.y * JC;
+    double acc[JC][PP];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+        for (int q = 0; q < PP; ++q) acc[jj][q] = 0.0;
+    const int64_t per = (dim + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = per * blockIdx.x, hi = std::min<int64_t>(lo + per, dim);
+    for (int64_t row = lo + threadIdx.x; row < hi; row += blockDim.x) {
+        double w[P];
+        load_drow<P>(W + row * P, w);
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj) {
+            if (j0 + jj >= nblk) break;
+            double xv[P];
+            load_drow<P>(X + ((size_t)(j0 + jj) * dim + row) * P, xv);
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+#pragma unroll
+                for (int c = 0; c < P; ++c) acc[jj][r * P + c] += xv[r] * w[c];
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+        for (int q = 0; q < PP; ++q) {
+            const double v = wave_sum(acc[jj][q]);
+            if (lane == 0) stage[(wid * JC + jj) * PP + q] = v;
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < JC * PP; t += blockDim.x) {
+        const int jj = t / PP, q = t % PP;
+        if (j0 + jj >= nblk) continue;
+        double v = 0.0;
+        for (int w8 = 0; w8 < (int)(blockDim.x >> 6); ++w8) v += stage[(w8 * JC + jj) * PP + q];
+        partial[((size_t)(j0 + jj) * gridDim.x + blockIdx.x) * PP + q] = v;
+    }
+}
+
 // out[j][pp] = sum over workgroups in order of partial[j][w][pp].
 __global__ void block_dots_finish(const double *__restrict__ partial, int nparts, int PP,
                                   double *__restrict__ out) {
@@ -241,8 +295,12 @@ struct BlockRun {
 
 template <int P>
 int dots(const BlockRun &R, const double *X, int nblk, const double *W, std::vector<double> &out) {
-    hipLaunchKernelGGL((block_dots_kernel<P>), dim3(kDotGrid, nblk), dim3(kDotBlock), 0, R.st, X,
-                       W, (int64_t)R.b->dim, R.partial());
+    if constexpr (P <= 4)
+        hipLaunchKernelGGL((block_dots_chunk_kernel<P>), dim3(kDotGrid, (nblk + kDotChunk - 1) / kDotChunk),
+                           dim3(kDotBlock), 0, R.st, X, W, (int64_t)R.b->dim, nblk, R.partial());
+    else
+        hipLaunchKernelGGL((block_dots_kernel<P>), dim3(kDotGrid, nblk), dim3(kDotBlock), 0, R.st,
+                           X, W, (int64_t)R.b->dim, R.partial());
     hipLaunchKernelGGL(block_dots_finish, dim3(nblk), dim3(P * P), 0, R.st, R.partial(),
                        kDotGrid, P * P, R.dots());
     HM_HIP(hipGetLastError());
