@@ -39,3 +39,36 @@ def test_sector_enumeration_and_multiplicity():
         total = sum(multiplicity(t) * count(N, two_s, (N * two_s - t) // 2) for t in tms)
         assert total == (two_s + 1) ** N
         assert [(N * two_s - t) // 2 for t in tms] == sectors.sector_lowerings(N, two_s)
+
+
+def test_autotune_candidates_and_bench_schedule_lookup(tmp_path, monkeypatch):
+    """Host logic around the block kernel's schedules: the candidate list
+    (staged splits only where the blocks fit and indices are 32-bit) and the
+    benchmark's use of the schedule stored with the committed counters (only
+    while the kernel source is unchanged, and traffic only for that schedule)."""
+    import json
+    import importlib.util
+    import os
+    from paper_0706_3293_amd import autotune
+    c28 = autotune.candidates(28)
+    assert all(len(s) == 4 and s[3] in (1, 2) for s in c28)
+    staged = [s for s in c28 if s[3] == 2]
+    assert staged and all(s[0] <= 11 and (s[2] <= 2 if s[0] == 11 else s[2] <= 4) for s in staged)
+    assert all(28 - s[0] <= 24 for s in c28)
+    assert not [s for s in autotune.candidates(36) if s[3] == 2]      # dim >= 2^32
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    path = tmp_path / "traffic.json"
+    entry = {"schedule": [13, 256, 8, 1], "bytes_per_launch": 123.0}
+    path.write_text(json.dumps({"kernel_sha1": bench.kernel_hash(),
+                                "entries": {"w/f32_mixed": entry}}))
+    monkeypatch.setattr(bench, "TRAFFIC", str(path))
+    assert bench.stored_schedule("w", "f32_mixed") == (13, 256, 8, 1)
+    assert bench.stored_schedule("w", "f64") is None
+    assert bench.measured_traffic("w", "f32_mixed", (13, 256, 8, 1)) == 123.0
+    assert bench.measured_traffic("w", "f32_mixed", (12, 256, 4, 1)) is None
+    path.write_text(json.dumps({"kernel_sha1": "0" * 40, "entries": {"w/f32_mixed": entry}}))
+    assert bench.stored_schedule("w", "f32_mixed") is None
+    assert bench.measured_traffic("w", "f32_mixed", (13, 256, 8, 1)) is None
