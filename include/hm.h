@@ -100,7 +100,7 @@ int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
  * sharing the other N-K sites form one contiguous block), the threads per
  * workgroup, and the rows each lane carries (rows with one low word and
  * different high words, sharing the low-word work).  0 keeps the default
- * (K = min(N, 12) for N <= 30, else 14; 256 threads; 4 rows per lane when
+ * (K = min(N, 12) for N <= 30, 13 for N <= 36, else 14; 256 threads; 4 rows per lane when
  * dim >= 2^22, else 1).  Must be called before the first device use of the
  * handle.  HM_EINVAL: K outside 1..min(14, N) or N - K > 24, block_threads
  * not 64/128/256, rows_per_lane not 1/2/4/8, or tables already built.  Used

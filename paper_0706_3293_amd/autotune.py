@@ -21,7 +21,7 @@ DEFAULT_CACHE = os.environ.get(
     "HM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hm_autotune.json"))
 
 
-TIE = 0.03      # relative timing difference treated as a tie
+TIE = 0.01      # relative timing difference treated as a tie
 
 
 def candidates(N):

@@ -539,8 +539,10 @@ __global__ __launch_bounds__(256) void hx_half_staged_kernel(
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Defaults measured on MI355X (one FP32 H x of J1-J2 rings): K = 13 beats 14
+// at N = 32 (14.5 vs 19.4 ms) and N = 36 (283 vs 365 ms).
 static int default_low_bits(int N) {
-    int K = N <= 30 ? std::min(N, 12) : 14;
+    int K = N <= 30 ? std::min(N, 12) : (N <= 36 ? 13 : 14);
     if (N - K > kHalfMaxHighBits) K = N - kHalfMaxHighBits;
     return K;
 }
