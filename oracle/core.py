@@ -33,6 +33,10 @@ def bind(path: str):
     lib.or_rank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p,
                             _intp]
     lib.or_rank.restype = ctypes.c_int64
+    lib.or_unrank_range.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p,
+                                    ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_uint8)]
+    lib.or_unrank_range.restype = ctypes.c_int
     lib.or_successor.argtypes = [ctypes.c_int, ctypes.c_int, _intp]
     lib.or_successor.restype = ctypes.c_int
     lib.or_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p,
@@ -105,6 +109,17 @@ class Subspace:
         if rc != 0:
             raise IndexError(f"index {i} outside [0, {self.dim})")
         return a.astype(np.int64)
+
+    def unrank_range(self, first: int, n: int) -> np.ndarray:
+        """Digits of basis states first .. first+n-1 as an (n, N) uint8 array,
+        each decoded on its own (Sec. 3.1)."""
+        out = np.zeros((n, self.N), dtype=np.uint8)
+        rc = self._lib.or_unrank_range(self.N, self.two_s, self.A,
+                                       _ptr(self.D, ctypes.c_int64), int(first), int(n),
+                                       _ptr(out, ctypes.c_uint8))
+        if rc != 0:
+            raise IndexError(f"range [{first}, {first + n}) outside [0, {self.dim})")
+        return out
 
     def rank(self, digits) -> int:
         """0-based index of the basis state with the given digits (Sec. 3.2)."""

@@ -68,69 +68,106 @@ static int64_t count_at(const int64_t *D, int N, int two_s, int n, int A)
 }
 
 /* ---------------------------------------------------------------------------
+ * Cumulative block bound for the codec of Secs. 3.1 and 3.2.
+ *
+ * Among the strings on sites 1..k with digit sum T, those whose digit on site
+ * k is m number D(k-1, T-m) (the other k-1 sites carry the rest, Eq. (E-3-c)).
+ * In the order of Eq. (E-3-a) site k is the most significant of the k, so the
+ * strings with a smaller digit on site k all come first.  below(k, T, n) is
+ * the number of strings on sites 1..k with sum T and digit on site k smaller
+ * than n, i.e. the position where the block with digit n starts.
+ * ------------------------------------------------------------------------- */
+static int64_t below(const int64_t *D, int N, int two_s, int k, int T, int n)
+{
+    int64_t start = 0;
+    for (int m = 0; m < n && m <= two_s; ++m)
+        start += count_at(D, N, two_s, k - 1, T - m);
+    return start;
+}
+
+/* ---------------------------------------------------------------------------
+ * Encoding |a_1 .. a_N> -> i, Sec. 3.2.
+ *
+ * The index of a state is the number of basis states that sort before it.
+ * A state b sorts before a exactly when, at the most significant site k where
+ * the two differ, b_k < a_k; b then agrees with a on sites k+1..N, so its
+ * sites 1..k carry the same digit sum T_k = a_1 + .. + a_k.  Those states
+ * number below(k, T_k, a_k) for each k, and the index is their total over
+ * k = 1..N (the k = 1 term is zero: one site holds its sum in one way).
+ * Sites are visited from k = 1 upward with T_k as a running prefix sum.
+ * Returns the 0-based index, or -1 if a digit is out of {0..2s} or the digits
+ * do not sum to A.
+ * ------------------------------------------------------------------------- */
+OR_EXPORT int64_t or_rank(int N, int two_s, int A, const int64_t *D,
+                          const int *a)
+{
+    int64_t index = 0;
+    int T = 0; /* digit sum of sites 1..k */
+    for (int k = 1; k <= N; ++k) {
+        const int digit = a[k - 1];
+        if (digit < 0 || digit > two_s)
+            return -1;
+        T += digit;
+        index += below(D, N, two_s, k, T, digit);
+    }
+    return T == A ? index : -1;
+}
+
+/* ---------------------------------------------------------------------------
  * Decoding i -> |a_1 .. a_N>, Sec. 3.1.
  *
- * Sites are fixed from the highest (k = N) down to k = 2.  At site k the
- * states that remain are split by the digit n placed there; the block with
- * digit n holds D(k-1, A_k - n) states, where A_k is the digit sum still to be
- * placed on sites 1..k.  The digit is the first n whose block contains the
- * remaining offset.  Site 1 takes whatever sum is left.  `a` receives
- * a[u-1] = a_u.  Returns 0, or -1 if i is not in [0, D(N, A)).
+ * The inverse of the count above, taken from the most significant site down.
+ * On site k (with T the digit sum left for sites 1..k and r the position left
+ * to reach among those strings) the blocks of strings with digit 0, 1, .., 2s
+ * on site k follow one another, block n starting at below(k, T, n).  The digit
+ * is the block that holds position r: the largest feasible n (n <= T, n <= 2s)
+ * whose block starts at or before r.  Position r - below(k, T, n) inside that
+ * block is what remains for sites 1..k-1.  On site 1 the rule leaves n = T.
+ * `a` receives a[u-1] = a_u.  Returns 0, or -1 if i is not in [0, D(N, A)).
  * ------------------------------------------------------------------------- */
 OR_EXPORT int or_unrank(int N, int two_s, int A, const int64_t *D, int64_t i,
                         int *a)
 {
     if (i < 0 || i >= count_at(D, N, two_s, N, A))
         return -1;
-    int64_t offset = i; /* states still to skip inside the current block */
-    int Ak = A;
-    for (int k = N; k >= 2; --k) {
-        int placed = -1;
-        for (int n = 0; n <= two_s; ++n) {
-            int64_t block = count_at(D, N, two_s, k - 1, Ak - n);
-            if (offset < block) {
-                placed = n;
-                break;
-            }
-            offset -= block;
-        }
-        if (placed < 0)
-            return -1;
-        a[k - 1] = placed;
-        Ak -= placed;
+    int64_t r = i;
+    int T = A;
+    for (int k = N; k >= 1; --k) {
+        int digit = 0;
+        for (int n = 1; n <= two_s && n <= T; ++n)
+            if (below(D, N, two_s, k, T, n) <= r)
+                digit = n;
+        r -= below(D, N, two_s, k, T, digit);
+        a[k - 1] = digit;
+        T -= digit;
     }
-    a[0] = Ak;
-    return 0;
+    return (r == 0 && T == 0) ? 0 : -1;
 }
 
-/* ---------------------------------------------------------------------------
- * Encoding |a_1 .. a_N> -> i, Sec. 3.2.
- *
- * The index is the number of basis states that sort before the given one.
- * Going from the highest site k = N down to k = 2, every state that agrees on
- * sites k+1..N but carries a smaller digit n < a_k on site k sorts before it;
- * there are D(k-1, A_k - n) of them for each such n.  Returns the 0-based
- * index, or -1 if a digit is out of {0..2s} or the digits do not sum to A.
- * ------------------------------------------------------------------------- */
-OR_EXPORT int64_t or_rank(int N, int two_s, int A, const int64_t *D,
-                          const int *a)
+/* Decoding of the consecutive indices first .. first+n-1 into rows of N
+ * digits (out[t * N + u] = a_{u+1} of index first + t); each index is decoded
+ * on its own with or_unrank.  Used to check device decoding over whole
+ * subspaces.  Returns 0, or -1 if an index is out of range. */
+OR_EXPORT int or_unrank_range(int N, int two_s, int A, const int64_t *D,
+                              int64_t first, int64_t n, uint8_t *out)
 {
-    int sum = 0;
-    for (int u = 0; u < N; ++u) {
-        if (a[u] < 0 || a[u] > two_s)
-            return -1;
-        sum += a[u];
+    int failed = 0;
+#pragma omp parallel
+    {
+        int *a = (int *)malloc(sizeof(int) * (size_t)N);
+#pragma omp for schedule(static)
+        for (int64_t t = 0; t < n; ++t) {
+            if (!a || or_unrank(N, two_s, A, D, first + t, a) != 0) {
+#pragma omp atomic write
+                failed = 1;
+                continue;
+            }
+            for (int u = 0; u < N; ++u)
+                out[(size_t)t * N + u] = (uint8_t)a[u];
+        }
+        free(a);
     }
-    if (sum != A)
-        return -1;
-    int64_t index = 0;
-    int Ak = A;
-    for (int k = N; k >= 2; --k) {
-        for (int n = 0; n < a[k - 1]; ++n)
-            index += count_at(D, N, two_s, k - 1, Ak - n);
-        Ak -= a[k - 1];
-    }
-    return index;
+    return failed ? -1 : 0;
 }
 
 /* ---------------------------------------------------------------------------

@@ -193,3 +193,30 @@ def test_single_site_and_extreme_subspaces():
         assert sub.dim == 1 and not sub.unrank(0).any()
         sub = oracle.Subspace(9, two_s, 9 * two_s)
         assert sub.dim == 1 and (sub.unrank(0) == two_s).all()
+
+
+@pytest.mark.parametrize("N,two_s", [(8, 1), (6, 2), (4, 3), (3, 7)])
+def test_unrank_range_matches_enumeration(N, two_s):
+    """The batch decoder returns the filtered, ascending full basis."""
+    for A in range(N * two_s + 1):
+        digits, _ = brute.enumerate_subspace(N, two_s, A)
+        sub = oracle.Subspace(N, two_s, A)
+        assert np.array_equal(sub.unrank_range(0, sub.dim), digits.astype(np.uint8)), A
+        if sub.dim > 2:
+            assert np.array_equal(sub.unrank_range(1, sub.dim - 2),
+                                  digits[1:-1].astype(np.uint8))
+
+
+def test_unrank_range_colex_closed_form():
+    """s=1/2, N=20, M=0: every decoded state's colex rank sum_t C(c_t, t)
+    equals its index (combinatorial number system)."""
+    sub = oracle.Subspace(20, 1, 10)
+    d = sub.unrank_range(0, sub.dim).astype(np.int64)
+    assert (d.sum(axis=1) == 10).all()
+    C = np.array([[math.comb(n, k) for k in range(21)] for n in range(21)], dtype=np.int64)
+    t = np.cumsum(d, axis=1)                      # ordinal of each set bit
+    pos = np.arange(20)[None, :]
+    colex = (d * C[pos, t]).sum(axis=1)
+    assert np.array_equal(colex, np.arange(sub.dim))
+    with pytest.raises(IndexError):
+        sub.unrank_range(sub.dim - 1, 2)

@@ -22,11 +22,14 @@ MUTANTS = {
                      "y += -1.0 * Juv * f * x_at(x, j);\n            }\n            /* s-(u) s+(v) */"),
     "ladder_factor": ("sqrt((double)cur[u] * (two_s - cur[u] + 1)) *",
                       "sqrt((double)cur[u] * (two_s - cur[u])) *"),
-    "rank_off_by_one": ("for (int n = 0; n < a[k - 1]; ++n)",
-                        "for (int n = 0; n <= a[k - 1] && n <= two_s; ++n)"),
-    "rank_wrong_row": ("index += count_at(D, N, two_s, k - 1, Ak - n);",
-                       "index += count_at(D, N, two_s, k - 1, Ak - n - 1);"),
-    "unrank_boundary": ("if (offset < block) {", "if (offset <= block && block > 0) {"),
+    "rank_off_by_one": ("index += below(D, N, two_s, k, T, digit);",
+                        "index += below(D, N, two_s, k, T, digit + 1);"),
+    "rank_wrong_prefix": ("index += below(D, N, two_s, k, T, digit);",
+                          "index += below(D, N, two_s, k, T - digit, digit);"),
+    "block_wrong_row": ("start += count_at(D, N, two_s, k - 1, T - m);",
+                        "start += count_at(D, N, two_s, k, T - m);"),
+    "unrank_boundary": ("if (below(D, N, two_s, k, T, n) <= r)",
+                        "if (below(D, N, two_s, k, T, n) < r)"),
     "count_recursion": ("for (int k = 0; k <= two_s; ++k) {\n                int prev",
                         "for (int k = 0; k < two_s; ++k) {\n                int prev"),
     "successor_refill": ("int put = balls < two_s ? balls : two_s;",
