@@ -88,6 +88,13 @@ int hm_basis_init(int32_t N, int32_t two_s, int32_t two_M, hm_basis *out);
  * with the handle must have completed.  NULL is accepted. */
 int hm_basis_free(hm_basis h);
 
+/* Number of coupling lists the handle currently keeps on the device.  Each
+ * distinct J passed with the handle is uploaded once (with the spin-1/2 block
+ * kernel's neighbour table); at most 4 are kept, least recently used first
+ * out, and one still in use by a running call is freed when that call
+ * returns.  HM_EINVAL: null argument. */
+int hm_basis_cached_couplings(hm_basis h, int32_t *count);
+
 /* Dimension D(N, A) of the subspace. */
 int hm_basis_dim(hm_basis h, int64_t *dim);
 
@@ -274,16 +281,33 @@ int hm_block_lanczos(hm_basis h, const double *J, const double *d_X0, int32_t p,
 int hm_tridiag_ritz(int32_t k, const double *alpha, const double *beta,
                     double *values, double *weights);
 
+/* Eigenvalues (ascending) of the symmetric block tridiagonal matrix of a block
+ * Lanczos run: n diagonal blocks A (host, n x p x p row-major) and n - 1
+ * sub-diagonal blocks B (host, (n - 1) x p x p; block k is the (k+1, k)
+ * block, whose transpose sits above the diagonal).  values: host array of
+ * n * p doubles.  Host FP64: Householder reduction of the assembled matrix to
+ * tridiagonal form, then implicit shifted QR (the block form of the method's
+ * final tridiagonal step).  HM_EINVAL: n < 1, p < 1, null or non-finite
+ * input; HM_ERANGE: n * p > 20000. */
+int hm_block_tridiag_eigenvalues(int32_t n, int32_t p, const double *A,
+                                 const double *B, double *values);
+
 /* ---------------------------------------------------------------------------
  * Bond correlations <psi| s(u).s(v) |psi> for nb bonds (uv: host int32
  * [nb][2], 0 <= u != v < N), psi a device FP64 vector of dim entries.
  * By Hellmann-Feynman dE0/dJ_uv = -<s(u).s(v)> for the normalized ground
  * state.  corr: host array of nb doubles.  Rows are processed in the gather
  * form of Eq. (E-4-b); per-bond sums are reduced in a fixed order (bitwise
- * reproducible).  Synchronizes `stream`.
+ * reproducible).  d_work: caller-owned device workspace of at least
+ * hm_bond_corr_workspace(h, nb) bytes (the bond list, per-workgroup partial
+ * sums and the results live there; nothing is allocated per call).
+ * Synchronizes `stream`.
+ * HM_EINVAL: null pointers, nb < 0, a bond with u == v or a site outside
+ * 0..N-1.  HM_EWORKSPACE: work_bytes too small.  nb == 0 is a no-op.
  * ------------------------------------------------------------------------- */
+int hm_bond_corr_workspace(hm_basis h, int32_t nb, size_t *bytes);
 int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
-                 double *corr, void *stream);
+                 void *d_work, size_t work_bytes, double *corr, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Batched Lanczos: ninst independent problems, each with nvec start vectors,

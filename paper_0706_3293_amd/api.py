@@ -3,7 +3,9 @@
 Every step of the hot path runs in the HIP kernels of libhm.so; torch is used
 only to hold device memory and to name the current HIP stream.
 """
+import atexit
 import ctypes
+import weakref
 from dataclasses import dataclass
 from fractions import Fraction
 
@@ -15,6 +17,33 @@ from ._lib import HM_F32, HM_F64, HM_PREC_F32_MIXED, HM_PREC_F64, check, lib
 
 PRECISIONS = {"f64": HM_PREC_F64, "fp64": HM_PREC_F64,
               "f32_mixed": HM_PREC_F32_MIXED, "mixed": HM_PREC_F32_MIXED}
+
+
+# Live basis handles.  At interpreter exit they are freed by an atexit hook,
+# which runs before torch's own exit handlers and long before the HIP runtime
+# and any profiler attached to it are torn down; handles still alive after
+# that (objects finalized during interpreter shutdown) are left to the
+# process exit instead of calling into the runtime.
+_live = weakref.WeakSet()
+_exiting = False
+
+
+def _free_all_at_exit():
+    global _exiting
+    _exiting = True
+    handles = list(_live)
+    if not handles or _lib._lib is None:
+        return
+    try:
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for b in handles:
+        b._free()
+
+
+atexit.register(_free_all_at_exit)
 
 
 def _stream():
@@ -74,16 +103,32 @@ class Basis:
         self.two_M = int(two_M)
         self.dim = dim.value
         self._work = {}
+        _live.add(self)
+
+    def _free(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        self._work = {}
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.hm_basis_free(h)
+
+    def free(self):
+        """Release the handle now (waits for the device first); the object
+        is unusable afterwards."""
+        if getattr(self, "_h", None) is not None:
+            torch.cuda.synchronize()
+            self._free()
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib._lib is not None:
+        if _exiting:
+            return                    # freed by the exit hook, or left to exit
+        if getattr(self, "_h", None) is not None:
             try:
-                torch.cuda.synchronize() if torch.cuda.is_available() else None
+                if torch.cuda.is_available() and torch.cuda.is_initialized():
+                    torch.cuda.synchronize()
             except Exception:
                 pass
-            _lib._lib.hm_basis_free(h)
-            self._h = None
+            self._free()
 
     @property
     def handle(self):
@@ -235,13 +280,24 @@ class Basis:
         return block_tridiag_eigenvalues(A, B)[:count]
 
     def bond_corr(self, bonds, psi: torch.Tensor) -> np.ndarray:
+        """<psi| s(u).s(v) |psi> for each bond (u, v) (device FP64 psi)."""
         uv = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
         out = np.zeros(uv.shape[0])
+        n = ctypes.c_size_t()
+        check(lib().hm_bond_corr_workspace(self._h, uv.shape[0], ctypes.byref(n)))
+        work = torch.empty(max(n.value, 1), dtype=torch.uint8, device=psi.device)
         check(lib().hm_bond_corr(self._h, uv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                 uv.shape[0], _dptr(psi.contiguous()),
+                                 uv.shape[0], _dptr(psi.contiguous()), _dptr(work),
+                                 work.numel(),
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                  _stream()))
         return out
+
+    def cached_couplings(self) -> int:
+        """Coupling lists the handle keeps on the device (at most 4)."""
+        n = ctypes.c_int32()
+        check(lib().hm_basis_cached_couplings(self._h, ctypes.byref(n)))
+        return n.value
 
 
 def tridiag_lowest(alpha, beta):
@@ -271,17 +327,18 @@ def tridiag_ritz(alpha, beta):
 
 def block_tridiag_eigenvalues(A, B) -> np.ndarray:
     """Eigenvalues (ascending) of the symmetric block tridiagonal matrix with
-    diagonal blocks A[k] and sub-diagonal blocks B[k] (block k+1, k)."""
-    A = np.asarray(A, dtype=np.float64)
-    B = np.asarray(B, dtype=np.float64)
+    diagonal blocks A[k] and sub-diagonal blocks B[k] (block k+1, k), by the
+    library's host solver."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
     n, p = A.shape[0], A.shape[1]
-    T = np.zeros((n * p, n * p))
-    for k in range(n):
-        T[k * p:(k + 1) * p, k * p:(k + 1) * p] = A[k]
-        if k + 1 < n:
-            T[(k + 1) * p:(k + 2) * p, k * p:(k + 1) * p] = B[k]
-            T[k * p:(k + 1) * p, (k + 1) * p:(k + 2) * p] = B[k].T
-    return np.linalg.eigvalsh(T)
+    B = np.ascontiguousarray(np.asarray(B, dtype=np.float64)[: max(n - 1, 0)])
+    if B.shape[0] == 0:
+        B = np.zeros((1, p, p))
+    vals = np.zeros(n * p)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().hm_block_tridiag_eigenvalues(n, p, A.ctypes.data_as(dp), B.ctypes.data_as(dp),
+                                             vals.ctypes.data_as(dp)))
+    return vals
 
 
 def set_timing(enable: bool):

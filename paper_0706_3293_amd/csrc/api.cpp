@@ -49,8 +49,9 @@ int hm_apply(hm_basis h, const double *J, const void *d_x, void *d_y, int32_t dt
     if (dtype != HM_F64 && dtype != HM_F32) return fail(HM_EINVAL, "unknown dtype %d", dtype);
     if (d_x == d_y) return fail(HM_EINVAL, "x and y must not alias");
     hm::Basis *b = &h->impl;
-    const hm::Couplings *c = nullptr;
-    HM_TRY(hm::get_couplings(b, J, &c));
+    hm::CouplingsRef cref;
+    HM_TRY(hm::get_couplings(b, J, &cref));
+    const hm::Couplings *c = cref.get();
     hm::HxPass p;
     p.x = d_x;
     p.y = d_y;
@@ -68,8 +69,9 @@ int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y, int
     if (d_x == d_y) return fail(HM_EINVAL, "x and y must not alias");
     hm::Basis *b = &h->impl;
     if (kernel < 1 || kernel > 4) return fail(HM_EINVAL, "kernel must be 1, 2, 3 or 4");
-    const hm::Couplings *c = nullptr;
-    HM_TRY(hm::get_couplings(b, J, &c));
+    hm::CouplingsRef cref;
+    HM_TRY(hm::get_couplings(b, J, &cref));
+    const hm::Couplings *c = cref.get();
     if (kernel >= 3) return hm::launch_hx_ablation(b, c, dtype, kernel, d_x, d_y, (hipStream_t)stream);
     const int k = hm::choose_kernel(b, c, kernel);
     if (k < 0) return fail(HM_EINVAL, "kernel %d not applicable", kernel);
@@ -79,8 +81,34 @@ int hm_apply_kernel(hm_basis h, const double *J, const void *d_x, void *d_y, int
     return hm::launch_hx(b, c, dtype, k, p, (hipStream_t)stream);
 }
 
-int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi, double *corr,
-                 void *stream) {
+// Layout of the bond-correlation workspace: the sorted bond list, the
+// per-workgroup partial sums of one chunk of bonds, the results.
+static void bond_corr_layout(const hm::Basis *b, int nb, size_t *uv_off, size_t *part_off,
+                             size_t *out_off, size_t *total) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int chunk = hm::bond_corr_max_bonds();
+    const int nchunk = nb < chunk ? nb : chunk;
+    size_t off = 0;
+    *uv_off = off;
+    off = al(off + sizeof(int32_t) * 2 * (size_t)nb);
+    *part_off = off;
+    off = al(off + sizeof(double) * (size_t)hm::bond_corr_blocks(b) * (size_t)nchunk);
+    *out_off = off;
+    off = al(off + sizeof(double) * (size_t)nb);
+    *total = off;
+}
+
+int hm_bond_corr_workspace(hm_basis h, int32_t nb, size_t *bytes) {
+    hm::clear_error();
+    if (!h || !bytes) return fail(HM_EINVAL, "null argument");
+    if (nb < 0) return fail(HM_EINVAL, "nb < 0");
+    size_t a, b2, c;
+    bond_corr_layout(&h->impl, nb, &a, &b2, &c, bytes);
+    return HM_OK;
+}
+
+int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
+                 void *d_work, size_t work_bytes, double *corr, void *stream) {
     hm::clear_error();
     if (!h || !uv || !d_psi || !corr) return fail(HM_EINVAL, "null argument");
     if (nb < 0) return fail(HM_EINVAL, "nb < 0");
@@ -91,6 +119,11 @@ int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
         if (u < 0 || v < 0 || u >= b->N || v >= b->N || u == v)
             return fail(HM_EINVAL, "bad bond %d: (%d, %d)", i, u, v);
     }
+    size_t uv_off, part_off, out_off, total;
+    bond_corr_layout(b, nb, &uv_off, &part_off, &out_off, &total);
+    if (!d_work) return fail(HM_EINVAL, "null workspace");
+    if (work_bytes < total)
+        return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, total);
     {
         std::lock_guard<std::mutex> lock(b->mu);
         HM_TRY(hm::device_prepare(b));
@@ -104,16 +137,12 @@ int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
         sorted[2 * i] = u < v ? u : v;
         sorted[2 * i + 1] = u < v ? v : u;
     }
-    int32_t *d_uv = nullptr;
-    double *d_partial = nullptr, *d_out = nullptr;
-    const int nchunk = nb < chunk ? nb : chunk;
+    unsigned char *w = (unsigned char *)d_work;
+    int32_t *d_uv = (int32_t *)(w + uv_off);
+    double *d_partial = (double *)(w + part_off), *d_out = (double *)(w + out_off);
     int rc = HM_OK;
-    hipError_t e = hipMalloc(&d_uv, sizeof(int32_t) * 2 * (size_t)nb);
-    if (e == hipSuccess) e = hipMalloc(&d_partial, sizeof(double) * (size_t)nblocks * nchunk);
-    if (e == hipSuccess) e = hipMalloc(&d_out, sizeof(double) * (size_t)nb);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_uv, sorted.data(), sizeof(int32_t) * 2 * (size_t)nb,
-                           hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(d_uv, sorted.data(), sizeof(int32_t) * 2 * (size_t)nb,
+                                  hipMemcpyHostToDevice, st);
     if (e != hipSuccess) rc = fail(HM_EDEVICE, "bond correlation setup: %s", hipGetErrorString(e));
     for (int b0 = 0; rc == HM_OK && b0 < nb; b0 += chunk) {
         const int m = nb - b0 < chunk ? nb - b0 : chunk;
@@ -124,10 +153,7 @@ int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = fail(HM_EDEVICE, "bond correlation: %s", hipGetErrorString(e));
     }
-    (void)hipStreamSynchronize(st);
-    if (d_uv) (void)hipFree(d_uv);
-    if (d_partial) (void)hipFree(d_partial);
-    if (d_out) (void)hipFree(d_out);
+    (void)hipStreamSynchronize(st);   // the host bond list outlives the copy
     return rc;
 }
 

@@ -137,19 +137,23 @@ int device_prepare(Basis *b) {
 }
 
 // Bonds of J (u < v, J_uv != 0) in row-major upper-triangle order, uploaded
-// once per distinct J and kept until the handle is freed.
-int get_couplings(Basis *b, const double *J, const Couplings **out) {
+// once per distinct J.  The handle keeps the kCouplingCacheEntries most
+// recently used lists; older ones are dropped (and freed once no running call
+// holds them), so loops over many distinct J keep device memory bounded.
+int get_couplings(Basis *b, const double *J, CouplingsRef *out) {
     HM_TRY(validate_J(b, J));
     const int N = b->N;
     std::vector<double> key(J, J + (size_t)N * N);
     std::lock_guard<std::mutex> lock(b->mu);
     HM_TRY(device_prepare(b));
-    auto it = b->couplings.find(key);
-    if (it != b->couplings.end()) {
-        *out = it->second.get();
-        return HM_OK;
+    for (auto it = b->couplings.begin(); it != b->couplings.end(); ++it) {
+        if (it->first == key) {
+            b->couplings.splice(b->couplings.begin(), b->couplings, it);
+            *out = b->couplings.front().second;
+            return HM_OK;
+        }
     }
-    auto c = std::make_unique<Couplings>();
+    auto c = std::make_shared<Couplings>();
     for (int u = 0; u < N; ++u)
         for (int v = u + 1; v < N; ++v) {
             double x = J[(size_t)u * N + v];
@@ -168,8 +172,9 @@ int get_couplings(Basis *b, const double *J, const Couplings **out) {
         HM_HIP(hipMemcpy(c->dev, c->host.data(), c->host.size() * sizeof(BondDev),
                          hipMemcpyHostToDevice));
     }
-    *out = c.get();
-    b->couplings.emplace(std::move(key), std::move(c));
+    while (b->couplings.size() >= kCouplingCacheEntries) b->couplings.pop_back();
+    b->couplings.emplace_front(std::move(key), c);
+    *out = std::move(c);
     return HM_OK;
 }
 
@@ -252,6 +257,14 @@ int hm_basis_init(int32_t N, int32_t two_s, int32_t two_M, hm_basis *out) {
     for (int a = 1; a <= two_s; ++a)
         b.ladder[a] = std::sqrt((double)a * (double)(two_s - a + 1));
     *out = h;
+    return HM_OK;
+}
+
+int hm_basis_cached_couplings(hm_basis h, int32_t *count) {
+    hm::clear_error();
+    if (!h || !count) return fail(HM_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(h->impl.mu);
+    *count = (int32_t)h->impl.couplings.size();
     return HM_OK;
 }
 

@@ -713,14 +713,15 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
     unsigned char *w = (unsigned char *)d_work;
     hipStream_t st = (hipStream_t)stream;
     std::vector<hm::InstDesc> desc(ninst);
+    std::vector<hm::CouplingsRef> crefs(ninst);   // held until the run returns
     std::vector<hm::Item> items;
     uint32_t vec_off = 0;
     int max_prefix = 0, max_bonds = 0;
     for (int k = 0; k < ninst; ++k) {
         hm::Basis *b = &bases[k]->impl;
         if (!d_v0[k]) return fail(HM_EINVAL, "start vectors of instance %d are null", k);
-        const hm::Couplings *c = nullptr;
-        HM_TRY(hm::get_couplings(b, J[k], &c));   // validates J and prepares the device
+        HM_TRY(hm::get_couplings(b, J[k], &crefs[k]));   // validates J, prepares the device
+        const hm::Couplings *c = crefs[k].get();
         hm::InstDesc &d = desc[k];
         d.N = b->N;
         d.A = b->A;

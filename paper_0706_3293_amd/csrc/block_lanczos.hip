@@ -462,8 +462,9 @@ int hm_block_lanczos(hm_basis h, const double *J, const double *d_X0, int32_t p,
         return fail(HM_EWORKSPACE, "workspace %zu bytes < required %zu", work_bytes, L.total);
     if (b->dim < p) return fail(HM_EINVAL, "block size p=%d exceeds the dimension", p);
     HM_TRY(hm::check_lds(b));
-    const hm::Couplings *c = nullptr;
-    HM_TRY(hm::get_couplings(b, J, &c));
+    hm::CouplingsRef cref;
+    HM_TRY(hm::get_couplings(b, J, &cref));
+    const hm::Couplings *c = cref.get();
     std::fill(A, A + (size_t)steps * p * p, 0.0);
     std::fill(B, B + (size_t)steps * p * p, 0.0);
     hm::BlockRun R{b, c, p, steps, (unsigned char *)d_work, L, (hipStream_t)stream};

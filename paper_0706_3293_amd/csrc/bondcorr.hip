@@ -7,6 +7,10 @@
 // 1/2 * ladder factors * psi_j).  Per-bond sums are reduced wave by wave in a
 // fixed butterfly order into per-wave LDS slots, then per workgroup, then
 // over workgroups by a single workgroup: no atomics, bitwise reproducible.
+#include <cstring>
+#include <mutex>
+#include <vector>
+
 #include "device_common.h"
 #include "hm_internal.h"
 
@@ -90,44 +94,54 @@ int bond_corr_blocks(const Basis *b) {
 int bond_corr_max_bonds() { return kCorrMaxBonds; }
 
 template <typename I, int B>
-static void launch_t(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
-                     double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+static void launch_t(const Basis *b, const void *d_prefix, const double *d_ladder,
+                     const int32_t *d_uv, int nb, const double *d_psi, double *d_partial,
+                     int nblocks, double *d_out, hipStream_t st) {
     const size_t plen = b->prefix_len();
     size_t lds = ((plen * sizeof(I) + 15) / 16) * 16;
     lds += ((b->two_s + 2) * sizeof(double) + 15) / 16 * 16;
     lds += (size_t)(kCorrBlock / 64) * nb * sizeof(double);
     hipLaunchKernelGGL((bond_corr_kernel<I, B>), dim3(nblocks), dim3(kCorrBlock), lds, st,
-                       (const I *)b->d_prefix, b->d_ladder, d_uv, nb, b->N, b->A, b->two_s,
+                       (const I *)d_prefix, d_ladder, d_uv, nb, b->N, b->A, b->two_s,
                        (I)b->dim, d_psi, d_partial);
     hipLaunchKernelGGL(bond_corr_finish, dim3((nb + kCorrBlock - 1) / kCorrBlock),
                        dim3(kCorrBlock), 0, st, d_partial, nblocks, nb, d_out);
 }
 
 template <typename I>
-static int launch_bits(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
-                       double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+static int launch_bits(const Basis *b, const void *tp, const double *tl, const int32_t *d_uv,
+                       int nb, const double *d_psi, double *d_partial, int nblocks,
+                       double *d_out, hipStream_t st) {
     switch (b->bits) {
-        case 1: launch_t<I, 1>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 2: launch_t<I, 2>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 3: launch_t<I, 3>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 4: launch_t<I, 4>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 5: launch_t<I, 5>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 6: launch_t<I, 6>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 7: launch_t<I, 7>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
-        case 8: launch_t<I, 8>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 1: launch_t<I, 1>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 2: launch_t<I, 2>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 3: launch_t<I, 3>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 4: launch_t<I, 4>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 5: launch_t<I, 5>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 6: launch_t<I, 6>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 7: launch_t<I, 7>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
+        case 8: launch_t<I, 8>(b, tp, tl, d_uv, nb, d_psi, d_partial, nblocks, d_out, st); break;
         default: return fail(HM_ERANGE, "bits per digit %d unsupported", b->bits);
     }
     return HM_OK;
 }
 
-int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
-                     double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+static int corr_lds_check(const Basis *b, int nb) {
     const size_t lds = ((b->prefix_len() * (b->idx32 ? 4 : 8) + 15) / 16) * 16 +
                        ((b->two_s + 2) * sizeof(double) + 15) / 16 * 16 +
                        (size_t)(kCorrBlock / 64) * nb * sizeof(double);
     if (lds > 64 * 1024) return fail(HM_ERANGE, "bond correlation tables exceed LDS");
-    HM_TRY(b->idx32 ? launch_bits<uint32_t>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st)
-                    : launch_bits<uint64_t>(b, d_uv, nb, d_psi, d_partial, nblocks, d_out, st));
+    return HM_OK;
+}
+
+// Device tables from the handle (built on first device use).
+int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb, const double *d_psi,
+                     double *d_partial, int nblocks, double *d_out, hipStream_t st) {
+    HM_TRY(corr_lds_check(b, nb));
+    HM_TRY(b->idx32 ? launch_bits<uint32_t>(b, b->d_prefix, b->d_ladder, d_uv, nb, d_psi,
+                                            d_partial, nblocks, d_out, st)
+                    : launch_bits<uint64_t>(b, b->d_prefix, b->d_ladder, d_uv, nb, d_psi,
+                                            d_partial, nblocks, d_out, st));
     HM_HIP(hipGetLastError());
     return HM_OK;
 }

@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <map>
+#include <list>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -45,7 +45,10 @@ struct BondDev {
     double mJ2;   // -J/2: off-diagonal element is mJ2 * ladder factors
 };
 
-// One uploaded coupling list (immutable once built).
+// One uploaded coupling list (immutable once built).  Calls hold it through a
+// shared reference, so an entry evicted from the per-basis cache lives until
+// the last call that uses it returns; its device arrays are freed after a
+// device-wide synchronization (work enqueued with them may still be running).
 struct Couplings {
     int nb = 0;
     std::vector<BondDev> host;
@@ -55,10 +58,16 @@ struct Couplings {
     void *half = nullptr;
     void (*half_free)(void *) = nullptr;
     ~Couplings() {
+        if (dev || half) (void)hipDeviceSynchronize();
         if (dev) (void)hipFree(dev);
         if (half && half_free) half_free(half);
     }
 };
+using CouplingsRef = std::shared_ptr<Couplings>;
+
+// Distinct coupling lists a basis handle keeps on the device (least recently
+// used first out).
+constexpr size_t kCouplingCacheEntries = 4;
 
 // ---------------------------------------------------------------------------
 // Basis of H(M): count table, prefix tables, device copies.
@@ -90,7 +99,9 @@ struct Basis {
     int device = -1;
     void *d_prefix = nullptr;           // uint32 or uint64 copy of prefix
     double *d_ladder = nullptr;
-    std::map<std::vector<double>, std::unique_ptr<Couplings>> couplings;
+    // uploaded coupling lists, most recently used first (at most
+    // kCouplingCacheEntries)
+    std::list<std::pair<std::vector<double>, CouplingsRef>> couplings;
     // spin-1/2 block kernel: schedule (0 = default) and tables (first use)
     int half_K = 0;          // low bits per block word
     int half_block = 0;      // threads per workgroup (64, 128 or 256)
@@ -103,7 +114,7 @@ struct Basis {
 };
 
 int device_prepare(Basis *b);                      // device tables + device check
-int get_couplings(Basis *b, const double *J, const Couplings **out);
+int get_couplings(Basis *b, const double *J, CouplingsRef *out);
 int validate_J(const Basis *b, const double *J);
 
 // Host codec (Sec. 3.1 / 3.2), used by hm_unrank / hm_rank.

@@ -817,8 +817,9 @@ static int run_common(hm_basis h, const double *J, const double *d_v0, int32_t s
     if (steps < 1) return fail(HM_EINVAL, "steps must be >= 1");
     Basis *b = &h->impl;
     HM_TRY(check_opts(b, o));
-    const Couplings *c = nullptr;
-    HM_TRY(get_couplings(b, J, &c));
+    CouplingsRef cref;
+    HM_TRY(get_couplings(b, J, &cref));
+    const Couplings *c = cref.get();
     const bool small = o->kernel == 3 || (o->kernel == 0 && !g_timing && !o->full_reorth &&
                                           b->dim * (int64_t)std::max(c->nb, 1) <= kSmallAutoWork);
     const int kernel = small ? 1 : choose_kernel(b, c, o->kernel);

@@ -94,7 +94,79 @@ int tridiag_ritz(int k, const double *alpha, const double *beta, double *values,
     return HM_OK;
 }
 
+// Eigenvalues of the symmetric block tridiagonal matrix of a block Lanczos
+// run (the block form of the final tridiagonal step): assemble the dense
+// m x m matrix (m = n p), reduce it to tridiagonal form by Householder
+// similarity transformations (Golub and Van Loan, Matrix Computations,
+// Sec. 8.3.1: for column k the reflector P = I - tau v v^T, v_0 = 1, maps
+// T[k+1.., k] onto a multiple of e_1, and T <- P T P through
+// w = tau T v - (tau^2 / 2)(v^T T v) v, T <- T - v w^T - w v^T), then take
+// the eigenvalues of the tridiagonal by the implicit QR of tridiag_ritz.
+int block_tridiag_eigenvalues(int n, int p, const double *A, const double *B,
+                              double *values) {
+    if (n < 1 || p < 1) return fail(HM_EINVAL, "need n >= 1 and p >= 1");
+    if (!A || !values || (n > 1 && !B)) return fail(HM_EINVAL, "null argument");
+    const size_t m = (size_t)n * p;
+    if (m > 20000) return fail(HM_ERANGE, "block tridiagonal order %zu above 20000", m);
+    std::vector<double> T(m * m, 0.0);
+    auto at = [&](size_t i, size_t j) -> double & { return T[i * m + j]; };
+    for (int k = 0; k < n; ++k)
+        for (int r = 0; r < p; ++r)
+            for (int c = 0; c < p; ++c) {
+                const double a = A[((size_t)k * p + r) * p + c];
+                const double at_rc = A[((size_t)k * p + c) * p + r];
+                if (!std::isfinite(a)) return fail(HM_EINVAL, "non-finite block entry");
+                // the diagonal blocks are symmetric up to rounding: use the mean
+                at((size_t)k * p + r, (size_t)k * p + c) = 0.5 * (a + at_rc);
+                if (k + 1 < n) {
+                    const double b = B[((size_t)k * p + r) * p + c];   // block (k+1, k)
+                    if (!std::isfinite(b)) return fail(HM_EINVAL, "non-finite block entry");
+                    at((size_t)(k + 1) * p + r, (size_t)k * p + c) = b;
+                    at((size_t)k * p + c, (size_t)(k + 1) * p + r) = b;
+                }
+            }
+    std::vector<double> d(m), e(m, 0.0), v(m), w(m);
+    for (size_t k = 0; k + 2 < m; ++k) {
+        // reflector for x = T[k+1.., k]
+        const size_t q = k + 1;
+        double sigma = 0.0;
+        for (size_t i = q + 1; i < m; ++i) sigma += at(i, k) * at(i, k);
+        const double x0 = at(q, k);
+        if (sigma == 0.0) {                // already reduced in this column
+            e[k] = x0;
+            continue;
+        }
+        const double mu = std::sqrt(x0 * x0 + sigma);
+        const double v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+        const double tau = 2.0 * v0 * v0 / (sigma + v0 * v0);
+        v[q] = 1.0;
+        for (size_t i = q + 1; i < m; ++i) v[i] = at(i, k) / v0;
+        e[k] = mu;                         // P x = mu e_1 (sign absorbed: only |e| matters)
+        // w = tau T v on the trailing block, then w -= (tau/2)(w^T v) v
+        double wv = 0.0;
+        for (size_t i = q; i < m; ++i) {
+            double s = 0.0;
+            for (size_t j = q; j < m; ++j) s += at(i, j) * v[j];
+            w[i] = tau * s;
+            wv += w[i] * v[i];
+        }
+        for (size_t i = q; i < m; ++i) w[i] -= 0.5 * tau * wv * v[i];
+        for (size_t i = q; i < m; ++i)
+            for (size_t j = q; j < m; ++j) at(i, j) -= v[i] * w[j] + w[i] * v[j];
+    }
+    for (size_t i = 0; i < m; ++i) d[i] = at(i, i);
+    if (m >= 2) e[m - 2] = at(m - 1, m - 2);
+    std::vector<double> weights(m);
+    return tridiag_ritz((int)m, d.data(), e.data(), values, weights.data());
+}
+
 }  // namespace hm
+
+extern "C" int hm_block_tridiag_eigenvalues(int32_t n, int32_t p, const double *A,
+                                            const double *B, double *values) {
+    hm::clear_error();
+    return hm::block_tridiag_eigenvalues(n, p, A, B, values);
+}
 
 extern "C" int hm_tridiag_ritz(int32_t k, const double *alpha, const double *beta,
                                double *values, double *weights) {
