@@ -5,6 +5,10 @@ the repository root:  python tests/golden/make_oracle_golden.py
 Outputs (text JSON, floats printed with 17 significant digits):
   tests/golden/ring12_oracle.json        N=12 s=1/2 ring, 120 steps, full reorth
   tests/golden/all_to_all20_oracle.json  N=20 all-to-all, 300 steps, gradient
+  tests/golden/j1j2_ring32_oracle.json   N=32 J1-J2 ring (dim 601,080,390), the
+                                         first two Lanczos steps (alpha, beta);
+                                         about 30 GB of host memory, minutes
+Pass workload names to write only some of them.
 """
 import json
 import os
@@ -55,8 +59,24 @@ def all_to_all20():
                 residual=resid)
 
 
+def j1j2_ring32():
+    """The first two oracle Lanczos steps of the largest single-GPU workload:
+    two full H x applications on 601,080,390 rows (Sec. 4, Eq. (E-4-b))."""
+    N = 32
+    J = inputs.workload_couplings("j1j2_ring32")
+    sub = oracle.Subspace(N, 1, 16)
+    res = oracle.lanczos(sub, J, inputs.start_vector(sub.dim, 0), 2)
+    return dict(workload="j1j2_ring32", N=N, two_s=1, A=16, J1=-1.0, J2=-0.25,
+                dim=sub.dim, steps=2, full_reorth=False, seed=0,
+                alpha=_floats(res["alpha"]), beta=_floats(res["beta"]))
+
+
+WORKLOADS = {"ring12": ring12, "all_to_all20": all_to_all20, "j1j2_ring32": j1j2_ring32}
+
+
 def main():
-    for fn in (ring12, all_to_all20):
+    names = sys.argv[1:] or list(WORKLOADS)
+    for fn in (WORKLOADS[n] for n in names):
         t = time.time()
         data = fn()
         path = os.path.join(OUT, f"{data['workload']}_oracle.json")

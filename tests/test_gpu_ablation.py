@@ -1,5 +1,5 @@
 """GPU checks of the ablation kernels of hm_apply_kernel: the successor sweep
-(kernel 3, bitwise equal to the generic kernel) and the column scatter with
+(kernel 3, against the oracle and bitwise equal to the generic kernel) and the column scatter with
 atomic adds (kernel 4, equal up to the order of the additions)."""
 import numpy as np
 import pytest
@@ -30,16 +30,26 @@ CASES = [
 
 
 @pytest.mark.parametrize("N,two_s,A", CASES)
-def test_successor_sweep_is_bitwise_generic(N, two_s, A):
+def test_successor_sweep_matches_oracle_and_generic(N, two_s, A):
+    """Kernel 3 against the oracle's row gather (FP64 and FP32 tolerances),
+    and bitwise against the generic kernel (same per-row arithmetic)."""
+    import oracle
     from paper_0706_3293_amd import Basis
     print("successor sweep", N, two_s, A, flush=True)
     b = Basis(N, two_s=two_s, two_M=N * two_s - 2 * A)
+    sub = oracle.Subspace(N, two_s, A)
     J = _J(N, N + A)
-    x = torch.tensor(np.random.default_rng(A).uniform(-1, 1, b.dim), device="cuda")
-    for xd in (x, x.float()):
-        y1 = b.apply(J, xd, kernel=1)
-        y3 = b.apply(J, xd, kernel=3)
-        assert torch.equal(y1, y3)
+    xh = np.random.default_rng(A).uniform(-1, 1, b.dim)
+    scale = float(np.abs(sub.apply(np.abs(J), np.abs(xh))).max()) + 1e-300
+    x = torch.tensor(xh, device="cuda")
+    y3 = b.apply(J, x, kernel=3)
+    assert np.abs(y3.cpu().numpy() - sub.apply(J, xh)).max() <= 1e-13 * scale
+    x32 = x.float()
+    y3f = b.apply(J, x32, kernel=3)
+    ref32 = sub.apply(J, x32.double().cpu().numpy())
+    assert np.abs(y3f.double().cpu().numpy() - ref32).max() <= 2e-6 * scale
+    for xd, yd in ((x, y3), (x32, y3f)):
+        assert torch.equal(b.apply(J, xd, kernel=1), yd)
 
 
 @pytest.mark.parametrize("N,two_s,A", CASES)

@@ -3,6 +3,9 @@
 Each (instance, start vector) pair must reproduce the single-instance path on
 the same inputs (FP32-mixed, tolerance for the different FP32 summation
 order), the oracle's FP64 energies, and the per-pair breakdown handling.
+Energies of converged runs are gated at 1e-7 relative to the oracle (the
+FP32-mixed target); the short 40-step runs compare coefficients, whose
+digits FP32 vectors limit to about 1e-6.
 """
 import numpy as np
 import pytest
@@ -49,23 +52,63 @@ def test_batched_heterogeneous_spin_half_vs_single_and_oracle(nvec):
             assert res.steps_done[k, r] == single.steps_done == ref["steps_done"], (k, r)
             n = min(10, single.steps_done)
             assert np.abs(res.alpha[k, r, :n] - single.alpha[:n]).max() < 1e-5
-            assert abs(res.E0[k, r] - ref["E0"]) <= 1e-6 * abs(ref["E0"])
+            m = min(5, n)                # the first coefficients (later ones drift, FP32)
+            assert np.abs(res.alpha[k, r, :m] - ref["alpha"][:m]).max() <= \
+                2e-6 * np.abs(ref["alpha"][:m]).max()
 
 
-def test_batched_spin_one_chains_subset():
-    """The spin-1 chain workload (a subset of its instances), 16 vectors."""
+@pytest.mark.parametrize("nvec", [4, 16])
+def test_batched_converged_energy_within_1e7_of_oracle(nvec):
+    """Runs long enough to converge (150 steps on subspaces of 252..3432
+    states): every pair's E0 within 1e-7 relative of the oracle's FP64
+    recurrence from the same start vector and step count."""
+    import oracle
+    from paper_0706_3293_amd import Basis, lanczos_batched
+    rng = np.random.default_rng(200 + nvec)
+    specs = [(10, 5), (12, 6), (14, 7), (13, 4), (11, 5)]
+    bases, Js, V0s = [], [], []
+    for N, A in specs:
+        b = Basis(N, two_s=1, two_M=N - 2 * A)
+        bases.append(b)
+        Js.append(_rand_J(N, rng))
+        V0s.append(rng.uniform(-1, 1, (nvec, b.dim)))
+    steps = 150
+    res = lanczos_batched(bases, Js, V0s, steps)
+    worst = 0.0
+    for k, (N, A) in enumerate(specs):
+        sub = oracle.Subspace(N, 1, A)
+        for r in range(nvec):
+            ref = oracle.lanczos(sub, Js[k], V0s[k][r], steps)
+            rel = abs(res.E0[k, r] - ref["E0"]) / abs(ref["E0"])
+            worst = max(worst, rel)
+            assert rel <= 1e-7, (k, r, rel)
+    print(f"batched converged, nvec {nvec}: worst relative E0 error {worst:.2e}", flush=True)
+
+
+def test_batched_spin_one_chains_subset_vs_oracle():
+    """The spin-1 chain workload at its own step count (80): the instances
+    of the seeded workload with N <= 12 run in one launch with all 16 start
+    vectors, and 4 vectors of each are checked against the oracle's FP64
+    recurrence (E0 within 1e-7 relative, same steps, first coefficients)."""
+    import oracle
     from paper_0706_3293_amd import Basis, inputs, lanczos_batched
-    inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)[:8]
+    inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)
+    inst = [d for d in inst if d["N"] <= 12][:8]
     bases = [Basis(d["N"], two_s=2, two_M=0) for d in inst]
     res = lanczos_batched(bases, [d["J"] for d in inst], [d["V0"] for d in inst], 80)
+    worst = 0.0
     for k, d in enumerate(inst):
-        e = res.E0[k]
-        ref = bases[k].lanczos(d["J"], torch.tensor(d["V0"][0], device="cuda"), 200)
-        print(f"instance {k}: N={d['N']} E0 spread {e.max() - e.min():.2e} "
-              f"vs f64 {e.min() - ref.E0:.2e}", flush=True)
-        assert np.all(np.isfinite(e))
-        assert e.min() >= ref.E0 - 1e-6 * abs(ref.E0)        # variational bound
-        assert abs(np.median(e) - ref.E0) <= 1e-5 * abs(ref.E0)
+        sub = oracle.Subspace(d["N"], 2, d["N"])
+        for r in range(4):
+            ref = oracle.lanczos(sub, d["J"], d["V0"][r], 80)
+            assert res.steps_done[k, r] == ref["steps_done"], (k, r)
+            rel = abs(res.E0[k, r] - ref["E0"]) / abs(ref["E0"])
+            worst = max(worst, rel)
+            assert rel <= 1e-7, (k, d["N"], r, rel)
+            assert np.abs(res.alpha[k, r, :5] - ref["alpha"][:5]).max() <= \
+                2e-6 * np.abs(ref["alpha"][:5]).max()
+    print(f"spin-1 chains subset ({len(inst)} instances, N <= 12): worst relative "
+          f"E0 error {worst:.2e}", flush=True)
 
 
 def test_batched_breakdown_and_padding():
@@ -94,8 +137,10 @@ def test_batched_rejects_bad_input():
         lanczos_batched([b1], [J4], [np.zeros((2, b1.dim))], 5)
 
 
-def test_batched_full_workload_runs():
-    """64 spin-1 chains x 16 vectors x 80 steps in one launch."""
+def test_batched_full_workload_vs_f64():
+    """64 spin-1 chains x 16 vectors x 80 steps in one launch; every pair's
+    E0 within 1e-7 relative of the instance's FP64 single-path ground state
+    (200 steps, converged)."""
     import time
     from paper_0706_3293_amd import Basis, inputs, lanczos_batched
     inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)
@@ -105,8 +150,13 @@ def test_batched_full_workload_runs():
     print(f"batched 64x16x80: {time.perf_counter() - t:.3f} s, "
           f"rows {sum(b.dim for b in bases)}", flush=True)
     assert np.all(np.isfinite(res.E0))
-    for k in range(64):
-        assert np.ptp(res.E0[k]) <= 1e-4 * abs(res.E0[k].mean())
+    worst = 0.0
+    for k, d in enumerate(inst):
+        ref = bases[k].lanczos(d["J"], torch.tensor(d["V0"][0], device="cuda"), 200)
+        rel = np.abs(res.E0[k] - ref.E0).max() / abs(ref.E0)
+        worst = max(worst, rel)
+        assert rel <= 1e-7, (k, d["N"], rel)
+    print(f"full workload: worst relative E0 error vs FP64 {worst:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("nvec", [8, 16])
@@ -124,7 +174,7 @@ def test_batched_spin_one_and_three_halves_vs_oracle(nvec):
             bases.append(b)
             Js.append(_rand_J(N, rng))
             V0s.append(rng.uniform(-1, 1, (nvec, b.dim)))
-        steps = 30
+        steps = 120                      # long enough to converge E0
         res = lanczos_batched(bases, Js, V0s, steps)
         for k, (N, two_s, A) in enumerate(specs):
             sub = oracle.Subspace(N, two_s, A)
@@ -133,4 +183,4 @@ def test_batched_spin_one_and_three_halves_vs_oracle(nvec):
                 assert res.steps_done[k, r] == ref["steps_done"], (k, r)
                 assert np.abs(res.alpha[k, r, :5] - ref["alpha"][:5]).max() <= \
                     2e-6 * np.abs(ref["alpha"][:5]).max()
-                assert abs(res.E0[k, r] - ref["E0"]) <= 1e-6 * abs(ref["E0"])
+                assert abs(res.E0[k, r] - ref["E0"]) <= 1e-7 * abs(ref["E0"])

@@ -140,7 +140,7 @@ def test_staged_blocks_rejected_where_blocks_do_not_fit():
 
 @pytest.mark.parametrize("N,schedule", [(28, None), (32, None), (32, (10, 256, 2, 2))])
 def test_block_kernel_full_size_sampled_rows(N, schedule):
-    """Workload sizes: sampled rows against the oracle, FP64 and FP32 (the
+    """Workload sizes: 2^20 sampled rows against the oracle, FP64 and FP32 (the
     default schedule, and at N=32 the staged schedule the autotuner picks
     for FP32 on MI355X)."""
     import oracle
@@ -151,7 +151,7 @@ def test_block_kernel_full_size_sampled_rows(N, schedule):
     sub = oracle.Subspace(N, 1, N // 2)
     rng = np.random.default_rng(3)
     x = rng.uniform(-1, 1, b.dim)
-    rows = np.sort(rng.integers(0, b.dim, 20000))
+    rows = np.sort(rng.integers(0, b.dim, 1 << 20))
     rows = np.concatenate([rows, [0, 1, b.dim - 2, b.dim - 1]])
     scale = float(np.abs(J).sum() / 2) * 1.0
     ref = sub.apply_rows(J, x, rows)

@@ -70,6 +70,30 @@ def test_device_codec_bit_exact(N, two_s, A):
     assert np.array_equal(back, idx)
 
 
+EXHAUSTIVE = [(24, 1, 12), (23, 1, 11), (20, 1, 7), (16, 1, 16), (12, 2, 12), (12, 2, 5),
+              (11, 2, 15), (10, 3, 15), (8, 4, 16), (7, 7, 24)]
+
+
+@pytest.mark.parametrize("N,two_s,A", EXHAUSTIVE)
+def test_device_codec_exhaustive_vs_oracle(N, two_s, A):
+    """Every state of the subspace: device decoding equals the oracle's
+    decoding digit for digit, and device encoding returns every index."""
+    import oracle
+    _say("codec exhaustive", N, two_s, A)
+    b = _basis(N, two_s, A)
+    sub = oracle.Subspace(N, two_s, A)
+    assert b.dim == sub.dim
+    digits = sub.unrank_range(0, sub.dim).astype(np.uint64)
+    ref = np.zeros(sub.dim, dtype=np.uint64)
+    for u in range(N):
+        ref |= digits[:, u] << np.uint64(u * b.bits)
+    idx = torch.arange(b.dim, dtype=torch.int64, device="cuda")
+    st = b.unrank_dev(idx)
+    assert np.array_equal(st.cpu().numpy().astype(np.uint64), ref)
+    back = b.rank_dev(torch.tensor(ref.astype(np.int64), device="cuda"))
+    assert torch.equal(back, idx)
+
+
 def test_device_codec_invalid_inputs():
     b = _basis(10, 2, 10)
     idx = torch.tensor([-1, b.dim, 0, b.dim - 1], dtype=torch.int64, device="cuda")
@@ -360,3 +384,23 @@ def test_graph_and_eager_runs_are_bitwise_equal(N, kernel, reorth):
                            kernel=kernel)
             assert r1.steps_done == r0.steps_done
             assert np.array_equal(r1.alpha, r0.alpha) and np.array_equal(r1.beta, r0.beta)
+
+
+def test_coupling_cache_stays_bounded():
+    """Many distinct coupling matrices on one handle (a finite-difference or
+    optimisation loop over J): the handle keeps at most 4 uploaded lists, and
+    results stay right across evictions, for both H x kernels and Lanczos."""
+    import oracle
+    from paper_0706_3293_amd import inputs
+    b = _basis(14, 1, 7)
+    sub = oracle.Subspace(14, 1, 7)
+    xh = np.random.default_rng(11).uniform(-1, 1, b.dim)
+    x = torch.tensor(xh, device="cuda")
+    Js = [inputs.ring_couplings(14, -1.0 - 0.01 * k, -0.2) for k in range(12)]
+    for k, J in enumerate(Js + Js[:3]):
+        for kernel in (1, 2):
+            y = b.apply(J, x, kernel=kernel).cpu().numpy()
+            assert np.abs(y - sub.apply(J, xh)).max() <= 1e-12 * _scale(sub, J, xh)
+        res = b.lanczos(J, x, 20)
+        assert res.steps_done == 20
+        assert 1 <= b.cached_couplings() <= 4, k
