@@ -1,13 +1,19 @@
 """Benchmark of the Lanczos hot path on one MI355X.
 
-Workload (default): the s=1/2 J1-J2 ring with N=28, J1=-1, J2=-0.5 in the
-M=0 subspace (dim 40,116,600), uniform[-1,1] start vector from seed 0.  One
-"step" is one Lanczos step: the fused H x pass (decode, diagonal, ladder
-flips, encode, gather), the alpha/beta reductions and the vector update.
-K steps are timed for the FP32-mixed path (vectors and matrix elements in
-FP32, dots/norms in FP64) and, separately, for the FP64 path; E0 of both is
-compared with the exact Majumdar-Ghosh value -3N/8 of this workload.
---workload j1j2_ring32 runs the N=32, J2=-0.25 ring (dim 601,080,390).
+Workload (default): the s=1/2 J1-J2 ring with N=32, J1=-1, J2=-0.25 in the
+M=0 subspace (dim 601,080,390, 2.4 GB per FP32 vector), uniform[-1,1] start
+vector from seed 0: the largest configuration of the measurement plan that
+fits one GPU.  One "step" is one Lanczos step: the H x pass (decode,
+diagonal, ladder flips, encode, gather), the alpha/beta reductions and the
+vector update.  K steps are timed for the FP32-mixed path (vectors and matrix
+elements in FP32, dots/norms in FP64) and, separately, for the FP64 path.
+
+Accuracy is measured outside the timed region on a full run of the
+workload's own length (150 steps at N=32, 200 at N=28) in both precisions:
+|E0(FP32-mixed) - E0(FP64)| absolute and relative, the first coefficients of
+the FP64 run against the oracle's stored values (two full oracle H x
+applications, tests/golden/), and at N=28 the exact energy -3N/8.
+--workload j1j2_ring28 runs the N=28, J2=-0.5 ring (dim 40,116,600).
 
 Prints one JSON line (one GPU).  `value` is the whole-job throughput of the
 FP32-mixed path in rows/s (dim x K / time, inputs already resident in HBM);
@@ -38,13 +44,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="j1j2_ring28", choices=["j1j2_ring28", "j1j2_ring32"])
+    ap.add_argument("--workload", default="j1j2_ring32", choices=["j1j2_ring28", "j1j2_ring32"])
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 generic, 2 spin-1/2 block")
     ap.add_argument("--no-tune", action="store_true", help="default schedule, no autotuning")
     ap.add_argument("--tune", action="store_true",
                     help="autotune even where a schedule is stored beside the counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 24)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 27,
+                    help="rows of the oracle's timed H x sample (about 15 s on 16 host threads)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the full-length accuracy runs")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also time one full oracle H x and one full oracle Lanczos step "
+                         "of the workload on the host (minutes at N=32)")
     ap.add_argument("--hx-repeats", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a 1 GiB device copy (profiling reference)")
@@ -92,19 +104,6 @@ def measured_traffic(workload, prec, schedule):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(N, J, x, rows):
-    """The oracle's row-gather H x on a random sample of rows (host cores)."""
-    import oracle
-    sub = oracle.Subspace(N, 1, N // 2)
-    sample = np.sort(np.random.default_rng(1).integers(0, sub.dim, rows))
-    t0 = time.perf_counter()
-    sub.apply_rows(J, x, sample)
-    dt = time.perf_counter() - t0
-    return dict(value=rows / dt, unit="rows/s", cores=oracle.max_threads(), kind="oracle",
-                sample=f"oracle FP64 H x of {rows} random rows of the same workload "
-                       f"({dt:.1f} s on the host)")
-
-
 # The oracle timed in a child process (no GPU), so that OMP_NUM_THREADS can be
 # set per run: rows/s of its H x on a row sample of the main workload, a full
 # N=12 Lanczos run and one full N=20 all-to-all H x.
@@ -131,20 +130,26 @@ if cfg["full_runs"]:
     v20 = np.random.default_rng(0).uniform(-1.0, 1.0, s20.dim)
     t0 = time.perf_counter(); s20.apply(J20, v20)
     out["all_to_all20_hx_s"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); sub.apply(J, x)
-    out["main_workload_full_hx_s"] = time.perf_counter() - t0
     Jp = np.array(cfg["Jp"]); sp = oracle.Subspace(20, 2, 7)
     vp = np.random.default_rng(0).uniform(-1.0, 1.0, sp.dim)
     t0 = time.perf_counter(); oracle.lanczos(sp, Jp, vp, 10)
     out["paper_vector_length_s_per_step"] = (time.perf_counter() - t0) / 10
+if cfg["oracle_full"]:
+    # the main workload in full: one H x, then one Lanczos step (the oracle's
+    # recurrence, one more H x and the vector updates)
+    t0 = time.perf_counter(); sub.apply(J, x)
+    out["main_workload_full_hx_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.lanczos(sub, J, x, 1)
+    out["main_workload_lanczos_step_s"] = time.perf_counter() - t0
 print(json.dumps(out))
 """
 
 
-def oracle_child(N, J, rows, threads, full_runs):
+def oracle_child(N, J, rows, threads, full_runs, oracle_full=False):
     import subprocess
     from paper_0706_3293_amd import inputs
     cfg = dict(root=ROOT, N=N, J=np.asarray(J).tolist(), rows=rows, full_runs=full_runs,
+               oracle_full=oracle_full,
                J12=inputs.ring_couplings(12, -1.0).tolist(),
                J20=inputs.all_to_all_couplings(20, 0)[0].tolist(),
                Jp=inputs.ring_couplings(20, -1.0).tolist())
@@ -152,7 +157,8 @@ def oracle_child(N, J, rows, threads, full_runs):
     if threads:
         env["OMP_NUM_THREADS"] = str(threads)
     res = subprocess.run([sys.executable, "-c", _ORACLE_CHILD], input=json.dumps(cfg),
-                         capture_output=True, text=True, env=env, timeout=300)
+                         capture_output=True, text=True, env=env,
+                         timeout=900 if oracle_full else 300)
     if res.returncode != 0:
         return {"error": res.stderr[-500:]}
     return json.loads(res.stdout.strip().splitlines()[-1])
@@ -184,6 +190,28 @@ def extras():
 
     from paper_0706_3293_amd import (Basis, BatchedProblem, ground_state_energy, inputs)
     out = {}
+    # the N=28 J1-J2 ring at the Majumdar-Ghosh point (dim 40,116,600): 200
+    # Lanczos steps in each precision with the schedules stored for it, E0
+    # against the exact -3N/8
+    J28 = inputs.workload_couplings("j1j2_ring28")
+    r28 = {}
+    for prec in ("f32_mixed", "f64"):
+        b = Basis(28, two_s=1, two_M=0)
+        sched = stored_schedule("j1j2_ring28", prec)
+        if sched is not None:
+            b.set_schedule(*sched)
+        v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+        b.lanczos(J28, v0, 3, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = b.lanczos(J28, v0, 200, precision=prec)
+        dt = time.perf_counter() - t0
+        r28[prec] = dict(ms_per_step=1e3 * dt / 200, E0=res.E0, schedule=sched,
+                         rel_dE0_vs_exact=abs(res.E0 + 10.5) / 10.5)
+        del v0, b
+    r28["mixed_over_f64_step_speedup"] = r28["f64"]["ms_per_step"] / r28["f32_mixed"]["ms_per_step"]
+    out["j1j2_ring28"] = r28
+    torch.cuda.empty_cache()
     # N=12 ring, 120 steps with full reorthogonalization, FP64
     b = Basis(12, two_s=1, two_M=0)
     J = inputs.ring_couplings(12, -1.0)
@@ -338,6 +366,17 @@ def extras():
     return out
 
 
+def load_golden(workload):
+    """The oracle's stored first Lanczos coefficients of the workload (written
+    by tests/golden/make_oracle_golden.py, which calls only the oracle)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle.json")
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -389,6 +428,7 @@ def main():
     v0_host = inputs.start_vector(D, w["seed"])
     v0 = torch.tensor(v0_host, device="cuda")
 
+    # the timed region: K steps of each precision, inputs resident in HBM
     results = {}
     for prec in ("f32_mixed", "f64"):
         b = bases[prec]
@@ -398,9 +438,37 @@ def main():
         res = b.lanczos(J, v0, args.steps, precision=prec, kernel=args.kernel)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        results[prec] = dict(ms_per_step=1e3 * dt / args.steps, E0=res.E0,
-                             steps_done=res.steps_done)
-        log(f"{prec}: {1e3 * dt / args.steps:.3f} ms/step E0={res.E0:.12f}")
+        results[prec] = dict(ms_per_step=1e3 * dt / args.steps, steps_done=res.steps_done)
+        log(f"{prec}: {1e3 * dt / args.steps:.3f} ms/step ({args.steps} steps timed)")
+
+    # accuracy, outside the timed region: the workload's full run length in
+    # both precisions, FP32-mixed against FP64, and FP64 against the oracle
+    acc = None
+    if not args.no_accuracy:
+        full = {}
+        for prec in ("f32_mixed", "f64"):
+            res = bases[prec].lanczos(J, v0, w["steps"], precision=prec, kernel=args.kernel)
+            full[prec] = res
+            log(f"{prec}: {w['steps']} steps, E0 = {res.E0:.15f}")
+        e32, e64 = full["f32_mixed"].E0, full["f64"].E0
+        acc = {"steps": w["steps"], "E0": {"f32_mixed": e32, "f64": e64},
+               "abs_dE0_mixed_vs_f64": abs(e32 - e64),
+               "rel_dE0_mixed_vs_f64": abs(e32 - e64) / abs(e64)}
+        if exact is not None:
+            acc["exact"] = exact
+            acc["abs_dE0_vs_exact"] = {p: abs(r.E0 - exact) for p, r in full.items()}
+            acc["rel_dE0_vs_exact"] = {p: abs(r.E0 - exact) / abs(exact)
+                                       for p, r in full.items()}
+        g = load_golden(args.workload)
+        if g is not None:
+            n = len(g["alpha"])
+            ra, rb = np.array(g["alpha"]), np.array(g["beta"])
+            acc["oracle_coefficients"] = {
+                p: {"steps": n,
+                    "rel_alpha": float(np.abs(r.alpha[:n] - ra).max() / np.abs(ra).max()),
+                    "rel_beta": float(np.abs(r.beta[:n] - rb).max() / np.abs(rb).max())}
+                for p, r in full.items()}
+        log(f"accuracy: {json.dumps(acc)}")
 
     # H x pass inside the Lanczos step, timed by HIP events on the call's stream
     hx = {}
@@ -426,16 +494,31 @@ def main():
 
     cpu = cpu_detail = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(N, J, v0_host, args.cpu_rows)
-        log(f"cpu baseline {cpu['value']:.3g} rows/s on {cpu['cores']} threads")
+        # the oracle on a bounded sample of the same workload's rows, and the
+        # GPU's FP64 H x of the same vector checked on those rows
+        import oracle
+        sub = oracle.Subspace(N, 1, N // 2)
+        sample = np.sort(np.random.default_rng(1).integers(0, D, args.cpu_rows))
+        t0 = time.perf_counter()
+        y_ref = sub.apply_rows(J, v0_host, sample)
+        dt = time.perf_counter() - t0
+        cpu = dict(value=args.cpu_rows / dt, unit="rows/s", cores=oracle.max_threads(),
+                   kind="oracle",
+                   sample=f"oracle FP64 H x of {args.cpu_rows} random rows of the same workload "
+                          f"(N={N}, dim {D}; {dt:.1f} s on the host)")
+        y = bases["f64"].apply(J, v0)
+        got = y[torch.tensor(sample, device="cuda")].cpu().numpy()
+        del y
+        cpu["gpu_f64_rows_max_abs_diff"] = float(np.abs(got - y_ref).max())
+        del got, y_ref, sample
+        log(f"cpu baseline {cpu['value']:.3g} rows/s on {cpu['cores']} threads; "
+            f"GPU FP64 H x on the sampled rows: max |diff| {cpu['gpu_f64_rows_max_abs_diff']:.2e}")
         cpu_detail = {"host": host_info(),
                       "one_thread": oracle_child(N, J, 1 << 18, 1, False),
-                      "all_threads": oracle_child(N, J, 1 << 22, 0, True)}
+                      "all_threads": oracle_child(N, J, 1 << 22, 0, True, args.oracle_full)}
         log(f"cpu baseline detail: {json.dumps(cpu_detail)}")
 
     mixed, f64 = results["f32_mixed"], results["f64"]
-    ref = exact if exact is not None else f64["E0"]
-    dE = {p: abs(r["E0"] - ref) for p, r in results.items()}
     h32 = hx["f32_mixed"]
     line = {
         "metric": METRIC,
@@ -451,24 +534,19 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: s=1/2 J1-J2 ring N={N} M=0 (dim {D}), "
-                               f"{args.steps} Lanczos steps, FP32-mixed (FP64 dots)",
+                               f"Lanczos steps, FP32-mixed (FP64 dots)",
                    "dim": D, "steps": args.steps, "parallelism": "single GPU",
                    "schedule": {p: s for p, s in schedules.items()}},
         "lanczos_steps_per_s": {"f32_mixed": 1e3 / mixed["ms_per_step"],
                                 "f64": 1e3 / f64["ms_per_step"]},
         "mixed_over_f64_step_speedup": f64["ms_per_step"] / mixed["ms_per_step"],
         "f64_rows_per_s": D / (f64["ms_per_step"] * 1e-3),
-        "E0": {"f32_mixed": mixed["E0"], "f64": f64["E0"], "exact": exact},
-        "abs_dE0": dE,
-        "rel_dE0": {p: v / abs(ref) for p, v in dE.items()},
-        "dE0_reference": "exact -3N/8" if exact is not None else "FP64 path",
+        "accuracy": acc,
         "hx_pass": hx,
         "roofline": {"bound": "hbm", "achieved": h32["alg_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": h32["alg_gbs"] / HBM_PEAK_GBS,
                      "traffic": h32["traffic_bytes"],
-                     "kernel": ("hx_half_staged_kernel<float, uint32, R, C, DOT=true>"
-                                if (schedules["f32_mixed"] or (0, 0, 0, 1))[3] == 2
-                                else "hx_half_kernel<float, uint32, R, DOT=true>"),
+                     "kernel": kernel_name(schedules["f32_mixed"]),
                      "schedule": schedules["f32_mixed"],
                      "alg_bytes_per_launch": h32["alg_bytes"]},
         "cpu_baseline": cpu,
@@ -476,6 +554,14 @@ def main():
         "other_workloads": other,
     }
     print(json.dumps(line), flush=True)
+
+
+def kernel_name(schedule):
+    """The FP32 H x kernel(s) a schedule runs (pass A of the Lanczos step)."""
+    split = (schedule or (0, 0, 0, 1))[3]
+    if split == 2:
+        return "hx_half_staged_kernel<float, uint32, R, C, DOT=true>"
+    return "hx_half_kernel<float, uint32, R, DOT=true>"
 
 
 if __name__ == "__main__":
