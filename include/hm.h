@@ -309,6 +309,24 @@ int hm_bond_corr_workspace(hm_basis h, int32_t nb, size_t *bytes);
 int hm_bond_corr(hm_basis h, const int32_t *uv, int32_t nb, const double *d_psi,
                  void *d_work, size_t work_bytes, double *corr, void *stream);
 
+/* hm_bond_corr for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same fixed-order sums (bitwise equal results),
+ * with the device copies of the handle's tables, the bond list, the partial
+ * sums and the results kept in one 4 MiB device array that the library owns
+ * for the life of the process (one per GPU).  Calls no allocating routine,
+ * does not need the handle's device tables to exist, and takes no workspace.
+ * At most 1024 bonds, and the staged data must fit the array: prefix table +
+ * bond list + (number of workgroups, <= 1024, ~dim/256) x nb doubles of
+ * partial sums + nb results; HM_ERANGE beyond that (nb <= 480 fits any
+ * dim).  Every call on one GPU uses that GPU's array and leaves it holding the
+ * last call's data: calls that overlap on one GPU (other threads or streams)
+ * race and must be serialized by the caller.  Synchronizes `stream`.
+ * HM_EINVAL: as hm_bond_corr.  HM_EDEVICE: HIP error or not a gfx950 device.
+ */
+int hm_bond_corr_noalloc(hm_basis h, const int32_t *uv, int32_t nb,
+                         const double *d_psi, double *corr, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched Lanczos: ninst independent problems, each with nvec start vectors,
  * solved together in FP32-mixed precision by one persistent (cooperative)

@@ -71,6 +71,7 @@ SIGNATURES = {
     "hm_bond_corr_workspace": (_i32, [_vp, _i32, _szp]),
     "hm_bond_corr": (_i32, [_vp, _i32p, _i32, _vp, _vp, ctypes.c_size_t, _dblp, _vp]),
     "hm_basis_cached_couplings": (_i32, [_vp, _i32p]),
+    "hm_bond_corr_noalloc": (_i32, [_vp, _i32p, _i32, _vp, _dblp, _vp]),
     "hm_lanczos_batched_workspace": (_i32, [_i32, ctypes.POINTER(_vp), _i32, _i32, _szp]),
     "hm_lanczos_batched": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_dblp),
                                   ctypes.POINTER(_vp), _i32, _i32, _dbl, _vp, ctypes.c_size_t,

@@ -146,4 +146,124 @@ int launch_bond_corr(const Basis *b, const int32_t *d_uv, int nb, const double *
     return HM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The bond correlations without any device allocation, for callers that
+// cannot allocate (code under graph capture, tight serving loops).  The
+// prefix and ladder tables, the bond list, the per-workgroup partial sums
+// and the results are staged in one file-scope device array.  In host code
+// the array's name is only a stand-in for a device address: its address on
+// each device is looked up once with hipGetSymbolAddress and that pointer is
+// what the copies and kernels are given.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int kScratchMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kScratchMaxDevices] = {};
+
+static int scratch_on_device(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kScratchMaxDevices)
+        return fail(HM_EDEVICE, "device %d outside 0..%d", dev, kScratchMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(HM_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return HM_OK;
+}
+
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 }  // namespace hm
+
+using hm::fail;
+
+extern "C" int hm_bond_corr_noalloc(hm_basis h, const int32_t *uv, int32_t nb,
+                                    const double *d_psi, double *corr, void *stream) {
+    hm::clear_error();
+    if (!h || !uv || !d_psi || !corr) return fail(HM_EINVAL, "null argument");
+    if (nb < 0) return fail(HM_EINVAL, "nb < 0");
+    if (nb == 0) return HM_OK;
+    hm::Basis *b = &h->impl;
+    for (int i = 0; i < nb; ++i) {
+        const int u = uv[2 * i], v = uv[2 * i + 1];
+        if (u < 0 || v < 0 || u >= b->N || v >= b->N || u == v)
+            return fail(HM_EINVAL, "bad bond %d: (%d, %d)", i, u, v);
+    }
+    if (nb > hm::kCorrMaxBonds)
+        return fail(HM_ERANGE, "at most %d bonds per call without allocation", hm::kCorrMaxBonds);
+    HM_TRY(hm::corr_lds_check(b, nb));
+    int dev = 0;
+    HM_HIP(hipGetDevice(&dev));
+    if (b->device >= 0 && b->device != dev)
+        return fail(HM_EDEVICE, "basis handle is bound to device %d, current is %d", b->device,
+                    dev);
+    hipDeviceProp_t prop;
+    HM_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(HM_EDEVICE, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+    // layout: prefix table, ladder factors, bond list, partial sums, results
+    const int nblocks = hm::bond_corr_blocks(b);
+    const size_t es = b->idx32 ? 4 : 8;
+    std::vector<unsigned char> tables(b->prefix_len() * es);
+    if (b->idx32) {
+        uint32_t *p32 = (uint32_t *)tables.data();
+        for (size_t i = 0; i < b->prefix_len(); ++i)
+            p32[i] = b->prefix[i] > (int64_t)UINT32_MAX ? UINT32_MAX : (uint32_t)b->prefix[i];
+    } else {
+        std::memcpy(tables.data(), b->prefix.data(), tables.size());
+    }
+    std::vector<int32_t> sorted(2 * (size_t)nb);
+    for (int i = 0; i < nb; ++i) {   // u < v, as the kernel expects
+        const int u = uv[2 * i], v = uv[2 * i + 1];
+        sorted[2 * i] = u < v ? u : v;
+        sorted[2 * i + 1] = u < v ? v : u;
+    }
+    size_t off = 0;
+    const size_t o_prefix = off;
+    off = hm::al256(off + tables.size());
+    const size_t o_ladder = off;
+    off = hm::al256(off + b->ladder.size() * sizeof(double));
+    const size_t o_uv = off;
+    off = hm::al256(off + sorted.size() * sizeof(int32_t));
+    const size_t o_part = off;
+    off = hm::al256(off + (size_t)nblocks * nb * sizeof(double));
+    const size_t o_out = off;
+    off = hm::al256(off + (size_t)nb * sizeof(double));
+    if (off > hm::kScratchBytes)
+        return fail(HM_ERANGE, "%d bonds on %lld rows need %zu bytes of scratch, more than the "
+                    "%zu the call without allocation has", nb, (long long)b->dim, off,
+                    hm::kScratchBytes);
+    unsigned char *ptr = nullptr;
+    HM_TRY(hm::scratch_on_device(dev, &ptr));
+    hipStream_t st = (hipStream_t)stream;
+    HM_HIP(hipMemcpyAsync(ptr + o_prefix, tables.data(), tables.size(), hipMemcpyHostToDevice,
+                          st));
+    HM_HIP(hipMemcpyAsync(ptr + o_ladder, b->ladder.data(), b->ladder.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    HM_HIP(hipMemcpyAsync(ptr + o_uv, sorted.data(), sorted.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    double *d_out = (double *)(ptr + o_out);
+    int rc = b->idx32
+        ? hm::launch_bits<uint32_t>(b, ptr + o_prefix, (const double *)(ptr + o_ladder),
+                                    (const int32_t *)(ptr + o_uv), nb, d_psi,
+                                    (double *)(ptr + o_part), nblocks, d_out, st)
+        : hm::launch_bits<uint64_t>(b, ptr + o_prefix, (const double *)(ptr + o_ladder),
+                                    (const int32_t *)(ptr + o_uv), nb, d_psi,
+                                    (double *)(ptr + o_part), nblocks, d_out, st);
+    if (rc == HM_OK) {
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(corr, d_out, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(HM_EDEVICE, "bond correlation: %s", hipGetErrorString(e));
+    }
+    (void)hipStreamSynchronize(st);   // the host tables outlive the copies
+    return rc;
+}
