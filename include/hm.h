@@ -193,10 +193,15 @@ typedef struct hm_lanczos_opts {
     int32_t full_reorth;  /* 1: classical Gram-Schmidt twice vs all v_j     */
     double breakdown_tol; /* relative; <= 0 selects 1e-12 (FP64) or 1e-6     *
                            * (FP32-mixed: the FP32 rounding floor of beta) */
-    int32_t use_graph;    /* 1: capture all steps in one hipGraph, built and
-                             instantiated anew on every call (same kernels,
-                             bitwise equal results; on MI355X the capture
-                             costs more than it saves for a single run)   */
+    int32_t use_graph;    /* 1: run all steps as one hipGraph.  The step
+                             loop is captured and instantiated on the first
+                             call with a given handle, coupling matrix,
+                             workspace address, step count and options,
+                             kept with the handle (its 4 most recent
+                             graphs) and replayed by later such calls; the
+                             start vector may change between calls (same
+                             kernels, bitwise equal results to direct
+                             launches)                                    */
     int32_t kernel;       /* 0: automatic choice (the one-workgroup run
                              without full_reorth when dim x bonds <=
                              16384, else the H x kernel that suits
@@ -341,17 +346,22 @@ int hm_bond_corr_noalloc(hm_basis h, const int32_t *uv, int32_t nb,
  *   E0           host array [ninst][nvec];
  *   steps_done   host array [ninst][nvec].
  * Each (instance, vector) pair runs its own recurrence; a breakdown stops
- * only that pair.  d_work: device workspace of at least
- * hm_lanczos_batched_workspace bytes.  Synchronizes `stream`.
+ * only that pair.  Schedule: the rows are cut into 256-row items and the
+ * persistent workgroups take `chunk` consecutive items at a time (1..64, 0 =
+ * 4), with `wg_per_cu` workgroups resident per compute unit (1..8, capped by
+ * occupancy; 0 = 4).  Every sum has a fixed order for a given schedule, so a
+ * run is reproducible; the autotuner picks the schedule per workload.
+ * d_work: device workspace of at least hm_lanczos_batched_workspace bytes.
+ * Synchronizes `stream`.  HM_EINVAL: bad arguments or schedule.
  * ------------------------------------------------------------------------- */
 int hm_lanczos_batched_workspace(int32_t ninst, const hm_basis *bases,
                                  int32_t nvec, int32_t steps, size_t *bytes);
 int hm_lanczos_batched(int32_t ninst, const hm_basis *bases,
                        const double *const *J, const double *const *d_v0,
                        int32_t nvec, int32_t steps, double breakdown_tol,
-                       void *d_work, size_t work_bytes, double *alpha,
-                       double *beta, double *E0, int32_t *steps_done,
-                       void *stream);
+                       int32_t chunk, int32_t wg_per_cu, void *d_work,
+                       size_t work_bytes, double *alpha, double *beta,
+                       double *E0, int32_t *steps_done, void *stream);
 
 /* Per-kernel timing of the last hm_lanczos call on this thread, measured
  * with HIP events on the call's stream: total milliseconds and launch count

@@ -74,8 +74,8 @@ SIGNATURES = {
     "hm_bond_corr_noalloc": (_i32, [_vp, _i32p, _i32, _vp, _dblp, _vp]),
     "hm_lanczos_batched_workspace": (_i32, [_i32, ctypes.POINTER(_vp), _i32, _i32, _szp]),
     "hm_lanczos_batched": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(_dblp),
-                                  ctypes.POINTER(_vp), _i32, _i32, _dbl, _vp, ctypes.c_size_t,
-                                  _dblp, _dblp, _dblp, _i32p, _vp]),
+                                  ctypes.POINTER(_vp), _i32, _i32, _dbl, _i32, _i32, _vp,
+                                  ctypes.c_size_t, _dblp, _dblp, _dblp, _i32p, _vp]),
     "hm_set_timing": (_i32, [_i32]),
     "hm_last_timing": (_i32, [_dblp, _i32p, _dblp]),
 }

@@ -1,4 +1,5 @@
-"""Autotuner for the spin-1/2 block kernel's schedule.
+"""Autotuners for the spin-1/2 block kernel's schedule and the batched
+persistent Lanczos launch.
 
 For a given problem (N, M, couplings, element type) every candidate schedule
 (low bits K, workgroup size, rows per lane, work split) is built on a fresh basis handle
@@ -117,3 +118,59 @@ def tuned_basis(N, J, two_M=0, dtype=torch.float32, **kw):
     b = Basis(N, two_s=1, two_M=two_M)
     b.set_schedule(*sched)
     return b, sched
+
+
+# --- batched persistent Lanczos -------------------------------------------
+# (items per chunk, workgroups per compute unit): the first is the default
+BATCH_CANDIDATES = [(4, 4)] + [(c, w) for w in (4, 2, 8, 1) for c in (1, 2, 4, 8, 16)
+                               if (c, w) != (4, 4)]
+
+
+def _batch_key(bases, nvec, steps):
+    shapes = ";".join(f"{b.N}/{b.two_s}/{b.two_M}" for b in bases)
+    h = hashlib.sha1(shapes.encode()).hexdigest()[:16]
+    return f"batched:n={len(bases)},nvec={nvec},steps={steps},shapes={h}"
+
+
+def tune_batched(bases, Js, V0s, steps, reps=2, cache=DEFAULT_CACHE, verbose=False):
+    """Best (chunk, workgroups per CU) of the batched persistent Lanczos for
+    this set of instances (their shapes, the number of start vectors and
+    steps), timed over whole runs; cached like the block kernel's schedules."""
+    import time
+    from .batched import BatchedProblem
+    nvec = int(V0s[0].shape[0])
+    key = _batch_key(bases, nvec, steps)
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            with open(cache) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        return tuple(table[key]["schedule"])
+    prob = BatchedProblem(bases, Js, V0s, steps)
+    trials = []
+    for sched in BATCH_CANDIDATES:
+        prob.schedule = sched
+        prob.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            prob.run()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        trials.append((sched, ms))
+        if verbose:
+            print(f"[autotune batched] chunk={sched[0]} wg/CU={sched[1]}: {ms:.2f} ms", flush=True)
+    fastest = min(ms for _, ms in trials)
+    best, best_ms = next((s, ms) for s, ms in trials if ms <= (1.0 + TIE) * fastest)
+    if cache:
+        table[key] = {"schedule": list(best), "ms": best_ms,
+                      "trials": [[list(s), m] for s, m in trials]}
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        except OSError:
+            pass
+    return best

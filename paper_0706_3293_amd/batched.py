@@ -30,7 +30,8 @@ class BatchedProblem:
     V0s: list of (nvec, dim_k) start vectors (numpy or torch), same nvec.
     """
 
-    def __init__(self, bases, Js, V0s, steps: int, tol: float = 0.0):
+    def __init__(self, bases, Js, V0s, steps: int, tol: float = 0.0, schedule=(0, 0)):
+        self.schedule = tuple(int(v) for v in schedule)   # (chunk, workgroups per CU)
         self.bases = list(bases)
         self.ninst = len(self.bases)
         self.nvec = int(V0s[0].shape[0])
@@ -62,6 +63,7 @@ class BatchedProblem:
         done = np.zeros((n, v), dtype=np.int32)
         dp = ctypes.POINTER(ctypes.c_double)
         check(lib().hm_lanczos_batched(n, self.handles, self.Jp, self.vp, v, s, self.tol,
+                                       self.schedule[0], self.schedule[1],
                                        ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
                                        alpha.ctypes.data_as(dp), beta.ctypes.data_as(dp),
                                        E0.ctypes.data_as(dp),
@@ -70,6 +72,8 @@ class BatchedProblem:
         return BatchedResult(alpha, beta, E0, done)
 
 
-def lanczos_batched(bases, Js, V0s, steps: int, tol: float = 0.0) -> BatchedResult:
-    """One batched run (see BatchedProblem)."""
-    return BatchedProblem(bases, Js, V0s, steps, tol).run()
+def lanczos_batched(bases, Js, V0s, steps: int, tol: float = 0.0,
+                    schedule=(0, 0)) -> BatchedResult:
+    """One batched run (see BatchedProblem); schedule = (items per chunk,
+    workgroups per compute unit), 0 for the defaults."""
+    return BatchedProblem(bases, Js, V0s, steps, tol, schedule).run()

@@ -1,6 +1,7 @@
 // Basis of H(M): count table, prefix tables and host encoding/decoding
 // (Sec. 3 of the paper), handle management, argument validation and the
 // per-handle cache of uploaded coupling lists.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -27,6 +28,9 @@ void clear_error() { g_error.clear(); }
 
 Basis::~Basis() {
     // Handles are freed after their work completed (documented contract).
+    for (Graph &g : graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
     if (d_prefix) (void)hipFree(d_prefix);
     if (d_ladder) (void)hipFree(d_ladder);
     couplings.clear();   // each Couplings frees its device arrays
@@ -153,7 +157,9 @@ int get_couplings(Basis *b, const double *J, CouplingsRef *out) {
             return HM_OK;
         }
     }
+    static std::atomic<uint64_t> next_serial{1};
     auto c = std::make_shared<Couplings>();
+    c->serial = next_serial.fetch_add(1);
     for (int u = 0; u < N; ++u)
         for (int v = u + 1; v < N; ++v) {
             double x = J[(size_t)u * N + v];

@@ -55,7 +55,8 @@ struct LdsBond {
     double mJ2;
 };
 constexpr int kStageWaves = 16;   // per-wave partial slots (workgroup <= 1024 threads)
-constexpr int kChunk = 4;         // items a workgroup takes at a time
+constexpr int kChunkDefault = 4;  // items a workgroup takes at a time (default)
+constexpr int kWgPerCuDefault = 4; // resident workgroups per compute unit (default)
 
 // Arrival counter, generation word and abort flag on separate 128-byte lines,
 // so the polling of gen does not contend with the arrivals on count.
@@ -82,6 +83,7 @@ struct BatchArgs {
     int *stopped;              // [npairs]: steps done at breakdown, 0 while running
     int max_prefix;            // entries of the largest prefix table
     int max_bonds;             // bonds of the largest coupling list
+    int chunk;                 // items a workgroup takes at a time
 };
 
 // Grid-wide barrier; returns false if the run was aborted (timeout).  One
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
     const int gwave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
     const bool lane0 = (threadIdx.x & 63) == 0;
-    // Workgroups take chunks of kChunk consecutive items, chunk c going to
+    // Workgroups take chunks of a.chunk consecutive items, chunk c going to
     // workgroup c % grid, so the grid sweeps the items roughly in order (a
     // narrow working set for the gathers).  Within a chunk, consecutive items
     // of one instance form a segment: threads add their rows' FP64
@@ -270,6 +272,7 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
     // segment, into the slot of the segment's first item.  All other slots
     // stay zero, so the per-pair sums over an instance's slots keep a fixed
     // order for a given grid.
+    const int kChunk = a.chunk;
     const int n_chunks = (a.n_items + kChunk - 1) / kChunk;
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const int i0 = c * kChunk, i1 = min(i0 + kChunk, a.n_items);
@@ -649,7 +652,8 @@ static int batch_layout(int ninst, const hm_basis *bases, int nvec, int steps, B
 }
 
 template <int NV, int B>
-static int launch_batched(BatchArgs &args, size_t lds, hipStream_t st, int *grid_out) {
+static int launch_batched(BatchArgs &args, size_t lds, int wg_per_cu, hipStream_t st,
+                          int *grid_out) {
     auto kern = batched_lanczos_kernel<NV, B>;
     int dev = 0, per_cu = 0;
     HM_HIP(hipGetDevice(&dev));
@@ -657,7 +661,8 @@ static int launch_batched(BatchArgs &args, size_t lds, hipStream_t st, int *grid
     HM_HIP(hipGetDeviceProperties(&prop, dev));
     HM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBatchBlock, lds));
     if (per_cu < 1) return fail(HM_ERANGE, "batched kernel does not fit on a compute unit");
-    int grid = std::min(per_cu, 4) * prop.multiProcessorCount;
+    // every workgroup of a cooperative launch must be resident at once
+    int grid = std::min(per_cu, wg_per_cu) * prop.multiProcessorCount;
     grid = std::min(grid, std::max(args.n_items, 1));
     *grid_out = grid;
     void *params[] = {&args};
@@ -667,12 +672,12 @@ static int launch_batched(BatchArgs &args, size_t lds, hipStream_t st, int *grid
 }
 
 template <int NV>
-static int dispatch_bits(int bits, BatchArgs &args, size_t lds, hipStream_t st, int *grid) {
+static int dispatch_bits(int bits, BatchArgs &args, size_t lds, int wg, hipStream_t st, int *grid) {
     switch (bits) {
-        case 1: return launch_batched<NV, 1>(args, lds, st, grid);
-        case 2: return launch_batched<NV, 2>(args, lds, st, grid);
-        case 3: return launch_batched<NV, 3>(args, lds, st, grid);
-        case 4: return launch_batched<NV, 4>(args, lds, st, grid);
+        case 1: return launch_batched<NV, 1>(args, lds, wg, st, grid);
+        case 2: return launch_batched<NV, 2>(args, lds, wg, st, grid);
+        case 3: return launch_batched<NV, 3>(args, lds, wg, st, grid);
+        case 4: return launch_batched<NV, 4>(args, lds, wg, st, grid);
         default: return fail(HM_ERANGE, "batched kernel supports up to 4 bits per digit");
     }
 }
@@ -701,11 +706,17 @@ int hm_lanczos_batched_workspace(int32_t ninst, const hm_basis *bases, int32_t n
 
 int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const *J,
                        const double *const *d_v0, int32_t nvec, int32_t steps,
-                       double breakdown_tol, void *d_work, size_t work_bytes, double *alpha,
-                       double *beta, double *E0, int32_t *steps_done, void *stream) {
+                       double breakdown_tol, int32_t chunk, int32_t wg_per_cu, void *d_work,
+                       size_t work_bytes, double *alpha, double *beta, double *E0,
+                       int32_t *steps_done, void *stream) {
     hm::clear_error();
     if (!J || !d_v0 || !d_work || !alpha || !beta || !E0 || !steps_done)
         return fail(HM_EINVAL, "null argument");
+    if (chunk == 0) chunk = hm::kChunkDefault;
+    if (wg_per_cu == 0) wg_per_cu = hm::kWgPerCuDefault;
+    if (chunk < 1 || chunk > 64) return fail(HM_EINVAL, "chunk %d outside 1..64", chunk);
+    if (wg_per_cu < 1 || wg_per_cu > 8)
+        return fail(HM_EINVAL, "workgroups per compute unit %d outside 1..8", wg_per_cu);
     hm::BatchLayout L;
     HM_TRY(hm::batch_layout(ninst, bases, nvec, steps, &L));
     if (work_bytes < L.total)
@@ -768,17 +779,18 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
     a.stopped = (int *)(w + L.stopped);
     a.max_prefix = max_prefix;
     a.max_bonds = max_bonds;
+    a.chunk = chunk;
     const size_t lds = ((size_t)(max_prefix * 4 + 15) / 16) * 16 + 32 * sizeof(double) +
                        (size_t)hm::kStageWaves * L.NV * sizeof(double) +
                        (size_t)max_bonds * sizeof(hm::LdsBond);
     const int bits = bases[0]->impl.bits;
     int grid = 0, rc;
     switch (L.NV) {
-        case 1: rc = hm::dispatch_bits<1>(bits, a, lds, st, &grid); break;
-        case 2: rc = hm::dispatch_bits<2>(bits, a, lds, st, &grid); break;
-        case 4: rc = hm::dispatch_bits<4>(bits, a, lds, st, &grid); break;
-        case 8: rc = hm::dispatch_bits<8>(bits, a, lds, st, &grid); break;
-        default: rc = hm::dispatch_bits<16>(bits, a, lds, st, &grid); break;
+        case 1: rc = hm::dispatch_bits<1>(bits, a, lds, wg_per_cu, st, &grid); break;
+        case 2: rc = hm::dispatch_bits<2>(bits, a, lds, wg_per_cu, st, &grid); break;
+        case 4: rc = hm::dispatch_bits<4>(bits, a, lds, wg_per_cu, st, &grid); break;
+        case 8: rc = hm::dispatch_bits<8>(bits, a, lds, wg_per_cu, st, &grid); break;
+        default: rc = hm::dispatch_bits<16>(bits, a, lds, wg_per_cu, st, &grid); break;
     }
     if (rc != HM_OK) return rc;
     HM_HIP(hipStreamSynchronize(st));

@@ -50,6 +50,7 @@ struct BondDev {
 // the last call that uses it returns; its device arrays are freed after a
 // device-wide synchronization (work enqueued with them may still be running).
 struct Couplings {
+    uint64_t serial = 0;      // unique per uploaded list (never reused)
     int nb = 0;
     std::vector<BondDev> host;
     BondDev *dev = nullptr;   // nb entries (nullptr when nb == 0)
@@ -109,9 +110,19 @@ struct Basis {
     int half_staging = 0;    // 0 automatic, 1 chunked items, 2 staged blocks
     void *half_tables = nullptr;
     void (*half_tables_free)(void *) = nullptr;
+    // instantiated graphs of Lanczos step loops, most recently used first,
+    // with the key of everything a capture bakes in (see lanczos.hip)
+    struct Graph {
+        std::vector<uint64_t> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::list<Graph> graphs;
 
     ~Basis();
 };
+
+// Step-loop graphs a basis handle keeps instantiated.
+constexpr size_t kGraphCacheEntries = 4;
 
 int device_prepare(Basis *b);                      // device tables + device check
 int get_couplings(Basis *b, const double *J, CouplingsRef *out);

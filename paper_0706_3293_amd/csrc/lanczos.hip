@@ -706,6 +706,56 @@ static int launch_small(const Run &R) {
     return HM_OK;
 }
 
+// The instantiated graph of the whole step loop for this run.  A capture
+// bakes in the kernels and every argument of the step loop: the coupling list
+// (by its serial number), the workspace address, the number of steps, the
+// precision, reorthogonalization, the H x kernel and the ground-state output
+// (the recompute pass), and through the basis handle its schedule and tables.
+// The start vector, the breakdown tolerance and the recompute coefficients
+// are not part of it: the initialization runs before the graph and leaves
+// them in the workspace.  A handle keeps kGraphCacheEntries graphs, least
+// recently used first out.
+template <typename T>
+static int step_graph(Run &R, hipGraphExec_t *out) {
+    Basis *b = R.b;
+    const std::vector<uint64_t> key = {R.c->serial, (uint64_t)(uintptr_t)R.w,
+                                       (uint64_t)R.steps, (uint64_t)R.prec, (uint64_t)R.reorth,
+                                       (uint64_t)R.kernel, (uint64_t)(uintptr_t)R.psi,
+                                       (uint64_t)sizeof(T)};
+    {
+        std::lock_guard<std::mutex> lock(b->mu);
+        for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it)
+            if (it->key == key) {
+                b->graphs.splice(b->graphs.begin(), b->graphs, it);
+                *out = b->graphs.front().exec;
+                return HM_OK;
+            }
+    }
+    hipGraph_t graph = nullptr;
+    HM_HIP(hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_steps<T>(R, 0, R.steps, nullptr);
+    hipError_t e = hipStreamEndCapture(R.st, &graph);
+    if (rc != HM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(HM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HM_EDEVICE, "graph instantiation: %s", hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(b->mu);
+    while (b->graphs.size() >= kGraphCacheEntries) {
+        // no launch of it can be pending when it is dropped: the run that
+        // used it synchronized its stream before returning
+        if (b->graphs.back().exec) (void)hipGraphExecDestroy(b->graphs.back().exec);
+        b->graphs.pop_back();
+    }
+    b->graphs.push_front(Basis::Graph{key, exec});
+    *out = exec;
+    return HM_OK;
+}
+
 template <typename T>
 static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done) {
     Basis *b = R.b;
@@ -752,21 +802,11 @@ static int run_lanczos(Run &R, double *alpha_h, double *beta_h, int *steps_done)
     }
     int rc = HM_OK;
     if (R.use_graph && !timing) {
-        hipGraph_t graph = nullptr;
+        // the step loop as one graph, captured and instantiated on the first
+        // call with this key and replayed by later calls
         hipGraphExec_t exec = nullptr;
-        HM_HIP(hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_steps<T>(R, 0, R.steps, nullptr);
-        hipError_t e = hipStreamEndCapture(R.st, &graph);
-        if (rc != HM_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
-        }
-        if (e != hipSuccess) return fail(HM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, R.st);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return fail(HM_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+        HM_TRY(step_graph<T>(R, &exec));
+        HM_HIP(hipGraphLaunch(exec, R.st));
     } else {
         rc = enqueue_steps<T>(R, 0, R.steps, timing ? &ev : nullptr);
         if (rc != HM_OK) return rc;

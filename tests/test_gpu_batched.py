@@ -184,3 +184,39 @@ def test_batched_spin_one_and_three_halves_vs_oracle(nvec):
                 assert np.abs(res.alpha[k, r, :5] - ref["alpha"][:5]).max() <= \
                     2e-6 * np.abs(ref["alpha"][:5]).max()
                 assert abs(res.E0[k, r] - ref["E0"]) <= 1e-7 * abs(ref["E0"])
+
+
+def test_batched_schedules_and_autotuner(tmp_path):
+    """The batched launch under other schedules (items per chunk, workgroups
+    per compute unit) gives the same steps and energies within the FP32-mixed
+    tolerance; the autotuner's choice is a candidate, is cached, and its run
+    matches the oracle at 1e-7 on converged runs (80 steps of the spin-1
+    chain workload's instances with N <= 12)."""
+    import oracle
+    from paper_0706_3293_amd import Basis, autotune, inputs, lanczos_batched
+    inst = inputs.batched_instances(lambda n: Basis(n, two_s=2, two_M=0).dim, count=64)
+    inst = [d for d in inst if d["N"] <= 12][:6]
+    bases = [Basis(d["N"], two_s=2, two_M=0) for d in inst]
+    Js = [d["J"] for d in inst]
+    V0s = [d["V0"][:4] for d in inst]
+    ref = lanczos_batched(bases, Js, V0s, 80)
+    for sched in ((1, 1), (16, 2), (2, 8)):
+        r = lanczos_batched(bases, Js, V0s, 80, schedule=sched)
+        assert np.array_equal(r.steps_done, ref.steps_done), sched
+        assert np.abs(r.E0 - ref.E0).max() <= 1e-7 * np.abs(ref.E0).max(), sched
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune_batched(bases, Js, V0s, 80, reps=1, cache=cache)
+    assert best in autotune.BATCH_CANDIDATES
+    assert autotune.tune_batched(bases, Js, V0s, 80, cache=cache) == best     # cached
+    r = lanczos_batched(bases, Js, V0s, 80, schedule=best)
+    for k, d in enumerate(inst):
+        sub = oracle.Subspace(d["N"], 2, d["N"])
+        for q in range(4):
+            o = oracle.lanczos(sub, d["J"], d["V0"][q], 80)
+            assert r.steps_done[k, q] == o["steps_done"]
+            assert abs(r.E0[k, q] - o["E0"]) <= 1e-7 * abs(o["E0"]), (k, q)
+    from paper_0706_3293_amd import _lib
+    with pytest.raises(_lib.HMError):
+        lanczos_batched(bases, Js, V0s, 5, schedule=(0, 9))
+    with pytest.raises(_lib.HMError):
+        lanczos_batched(bases, Js, V0s, 5, schedule=(65, 4))

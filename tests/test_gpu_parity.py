@@ -371,7 +371,8 @@ def test_graph_and_eager_runs_are_bitwise_equal(N, kernel, reorth):
     """A run captured in one hipGraph launches the same kernels as the eager
     run, so the coefficients agree bit for bit: large grids (finish kernels),
     small grids (pass B with the last-workgroup finish), with and without
-    reorthogonalization."""
+    reorthogonalization; the graph is captured once per handle and replayed,
+    also on another start vector."""
     from paper_0706_3293_amd import inputs
     b = _basis(N, 1, N // 2)
     J = inputs.ring_couplings(N, -1.0, -0.5)
@@ -384,6 +385,15 @@ def test_graph_and_eager_runs_are_bitwise_equal(N, kernel, reorth):
                            kernel=kernel)
             assert r1.steps_done == r0.steps_done
             assert np.array_equal(r1.alpha, r0.alpha) and np.array_equal(r1.beta, r0.beta)
+        # the cached graph replayed on another start vector (it bakes in the
+        # workspace, not v0), with eager work in between
+        v1 = torch.tensor(inputs.start_vector(b.dim, 4), device="cuda")
+        e1 = b.lanczos(J, v1, 60, precision=precision, full_reorth=reorth, use_graph=False,
+                       kernel=kernel)
+        g1 = b.lanczos(J, v1, 60, precision=precision, full_reorth=reorth, use_graph=True,
+                       kernel=kernel)
+        assert np.array_equal(g1.alpha, e1.alpha) and np.array_equal(g1.beta, e1.beta)
+        assert not np.array_equal(g1.alpha, r0.alpha)
 
 
 def test_coupling_cache_stays_bounded():
