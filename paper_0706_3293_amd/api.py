@@ -209,11 +209,13 @@ class Basis:
         return w
 
     def lanczos(self, J, v0: torch.Tensor, steps: int, precision="f64", full_reorth=False,
-                use_graph=True, tol=0.0, kernel=0) -> LanczosResult:
+                use_graph=False, tol=0.0, kernel=0) -> LanczosResult:
         """Lanczos from the device FP64 start vector v0 (Sec. 4's repeated H x).
         use_graph: replay the step loop as one hipGraph, captured on the first
-        call with these couplings, step count and options (bitwise equal to
-        direct launches; measured 0-3 % faster)."""
+        call with these couplings, step count and options and kept with the
+        handle (bitwise equal to direct launches).  Replays measured 0-3 %
+        faster than direct launches; the first call pays the capture, so it
+        pays off for repeated runs (more start vectors, repeated solves)."""
         assert v0.is_cuda and v0.dtype == torch.float64 and v0.shape == (self.dim,)
         v0 = v0.contiguous()
         opts = self._opts(precision, full_reorth, use_graph, tol, kernel)
