@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the full-length accuracy runs")
     ap.add_argument("--oracle-full", action="store_true",
-                    help="also time one full oracle H x and one full oracle Lanczos step "
+                    help="also time three full oracle H x and one full oracle Lanczos step "
                          "of the workload on the host (minutes at N=32)")
     ap.add_argument("--hx-repeats", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -134,22 +134,14 @@ if cfg["full_runs"]:
     vp = np.random.default_rng(0).uniform(-1.0, 1.0, sp.dim)
     t0 = time.perf_counter(); oracle.lanczos(sp, Jp, vp, 10)
     out["paper_vector_length_s_per_step"] = (time.perf_counter() - t0) / 10
-if cfg["oracle_full"]:
-    # the main workload in full: one H x, then one Lanczos step (the oracle's
-    # recurrence, one more H x and the vector updates)
-    t0 = time.perf_counter(); sub.apply(J, x)
-    out["main_workload_full_hx_s"] = time.perf_counter() - t0
-    t0 = time.perf_counter(); oracle.lanczos(sub, J, x, 1)
-    out["main_workload_lanczos_step_s"] = time.perf_counter() - t0
 print(json.dumps(out))
 """
 
 
-def oracle_child(N, J, rows, threads, full_runs, oracle_full=False):
+def oracle_child(N, J, rows, threads, full_runs):
     import subprocess
     from paper_0706_3293_amd import inputs
     cfg = dict(root=ROOT, N=N, J=np.asarray(J).tolist(), rows=rows, full_runs=full_runs,
-               oracle_full=oracle_full,
                J12=inputs.ring_couplings(12, -1.0).tolist(),
                J20=inputs.all_to_all_couplings(20, 0)[0].tolist(),
                Jp=inputs.ring_couplings(20, -1.0).tolist())
@@ -157,8 +149,7 @@ def oracle_child(N, J, rows, threads, full_runs, oracle_full=False):
     if threads:
         env["OMP_NUM_THREADS"] = str(threads)
     res = subprocess.run([sys.executable, "-c", _ORACLE_CHILD], input=json.dumps(cfg),
-                         capture_output=True, text=True, env=env,
-                         timeout=900 if oracle_full else 300)
+                         capture_output=True, text=True, env=env, timeout=300)
     if res.returncode != 0:
         return {"error": res.stderr[-500:]}
     return json.loads(res.stdout.strip().splitlines()[-1])
@@ -380,6 +371,26 @@ def extras():
     return out
 
 
+def oracle_full_size(N, J, x):
+    """The oracle on the whole workload, on all host threads: three full H x
+    applications and one full Lanczos step (minutes at N=32), each phase
+    reported as it ends."""
+    import oracle
+    sub = oracle.Subspace(N, 1, N // 2)
+    out = {"threads": oracle.max_threads(), "dim": sub.dim, "hx_s": []}
+    for k in range(3):
+        t0 = time.perf_counter()
+        sub.apply(J, x)
+        out["hx_s"].append(time.perf_counter() - t0)
+        log(f"oracle full H x {k + 1}/3: {out['hx_s'][-1]:.1f} s")
+    t0 = time.perf_counter()
+    oracle.lanczos(sub, J, x, 1)
+    out["lanczos_step_s"] = time.perf_counter() - t0
+    log(f"oracle full Lanczos step: {out['lanczos_step_s']:.1f} s")
+    out["hx_rows_per_s"] = sub.dim / min(out["hx_s"])
+    return out
+
+
 def load_golden(workload):
     """The oracle's stored first Lanczos coefficients of the workload (written
     by tests/golden/make_oracle_golden.py, which calls only the oracle)."""
@@ -529,7 +540,9 @@ def main():
             f"GPU FP64 H x on the sampled rows: max |diff| {cpu['gpu_f64_rows_max_abs_diff']:.2e}")
         cpu_detail = {"host": host_info(),
                       "one_thread": oracle_child(N, J, 1 << 18, 1, False),
-                      "all_threads": oracle_child(N, J, 1 << 22, 0, True, args.oracle_full)}
+                      "all_threads": oracle_child(N, J, 1 << 22, 0, True)}
+        if args.oracle_full:
+            cpu_detail["full_size"] = oracle_full_size(N, J, v0_host)
         log(f"cpu baseline detail: {json.dumps(cpu_detail)}")
 
     mixed, f64 = results["f32_mixed"], results["f64"]
