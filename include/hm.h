@@ -286,6 +286,25 @@ int hm_block_lanczos(hm_basis h, const double *J, const double *d_X0, int32_t p,
 int hm_tridiag_ritz(int32_t k, const double *alpha, const double *beta,
                     double *values, double *weights);
 
+/* Finite-temperature Lanczos sums (k_B = 1; the estimator of Jaklic and
+ * Prelovsek, Phys. Rev. B 49, 5065 (1994), built on the Ritz values and Gauss
+ * weights of hm_tridiag_ritz).  nruns Lanczos runs: run r contributes
+ * run_len[r] (level, weight) pairs, concatenated over the runs in run order
+ * in `levels` and `weights`, and every weight of run r is multiplied by
+ * run_scale[r] (for a run of one sector: the sector's multiplicity times its
+ * dimension over the number of start vectors).  With E_min the lowest level
+ * and b = scale * weight * exp(-(level - E_min) / T[t]), for each t:
+ *   Z[t] = sum b   (the partition function divided by exp(-E_min / T[t])),
+ *   E[t] = sum b level / Z[t],
+ *   C[t] = (sum b level^2 / Z[t] - E[t]^2) / T[t]^2.
+ * *E_min receives E_min.  Host FP64 with compensated sums; all
+ * pointers are host arrays owned by the caller.  HM_EINVAL: nruns < 1,
+ * nT < 1, a null pointer, a negative run length or scale, no pairs in all,
+ * a non-finite input, T[t] <= 0, or weights that sum to zero. */
+int hm_ftl_sums(int32_t nruns, const int32_t *run_len, const double *levels,
+                const double *weights, const double *run_scale, int32_t nT,
+                const double *T, double *Z, double *E, double *C, double *E_min);
+
 /* Eigenvalues (ascending) of the symmetric block tridiagonal matrix of a block
  * Lanczos run: n diagonal blocks A (host, n x p x p row-major) and n - 1
  * sub-diagonal blocks B (host, (n - 1) x p x p; block k is the (k+1, k)

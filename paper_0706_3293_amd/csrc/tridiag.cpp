@@ -160,6 +160,62 @@ int block_tridiag_eigenvalues(int n, int p, const double *A, const double *B,
     return tridiag_ritz((int)m, d.data(), e.data(), values, weights.data());
 }
 
+// Finite-temperature Lanczos sums over the Ritz values and Gauss weights of
+// many runs (see hm_ftl_sums in hm.h).
+int ftl_sums(int32_t nruns, const int32_t *run_len, const double *levels,
+             const double *weights, const double *run_scale, int32_t nT, const double *T,
+             double *Z, double *E, double *C, double *E_min) {
+    if (nruns < 1 || nT < 1 || !run_len || !levels || !weights || !run_scale || !T || !Z ||
+        !E || !C || !E_min)
+        return fail(HM_EINVAL, "ftl_sums: nruns and nT must be >= 1 and pointers non-null");
+    int64_t n = 0;
+    for (int32_t r = 0; r < nruns; ++r) {
+        if (run_len[r] < 0 || !std::isfinite(run_scale[r]) || run_scale[r] < 0.0)
+            return fail(HM_EINVAL, "ftl_sums: run %d has a negative length or a bad scale", r);
+        n += run_len[r];
+    }
+    if (n < 1) return fail(HM_EINVAL, "ftl_sums: no (level, weight) pairs");
+    double emin = levels[0];
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(levels[i]) || !std::isfinite(weights[i]))
+            return fail(HM_EINVAL, "ftl_sums: non-finite level or weight at %lld", (long long)i);
+        emin = std::min(emin, levels[i]);
+    }
+    for (int32_t t = 0; t < nT; ++t)
+        if (!std::isfinite(T[t]) || T[t] <= 0.0)
+            return fail(HM_EINVAL, "ftl_sums: temperature %d is not a positive number", t);
+    // compensated sums (Neumaier's variant of Kahan summation): C below
+    // cancels <H^2> against <H>^2, so the sums are kept to about one ulp
+    // however many levels there are
+    struct Sum {
+        double s = 0.0, c = 0.0;
+        void add(double v) {
+            const double t = s + v;
+            c += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+        double value() const { return s + c; }
+    };
+    for (int32_t t = 0; t < nT; ++t) {
+        Sum z, e, e2;
+        int64_t i = 0;
+        for (int32_t r = 0; r < nruns; ++r)
+            for (int32_t k = 0; k < run_len[r]; ++k, ++i) {
+                const double b = run_scale[r] * weights[i] * std::exp(-(levels[i] - emin) / T[t]);
+                z.add(b);
+                e.add(b * levels[i]);
+                e2.add(b * levels[i] * levels[i]);
+            }
+        const double zt = z.value();
+        if (!(zt > 0.0)) return fail(HM_EINVAL, "ftl_sums: the weights sum to zero");
+        Z[t] = zt;
+        E[t] = e.value() / zt;
+        C[t] = (e2.value() / zt - E[t] * E[t]) / (T[t] * T[t]);
+    }
+    *E_min = emin;
+    return HM_OK;
+}
+
 }  // namespace hm
 
 extern "C" int hm_block_tridiag_eigenvalues(int32_t n, int32_t p, const double *A,
@@ -172,4 +228,11 @@ extern "C" int hm_tridiag_ritz(int32_t k, const double *alpha, const double *bet
                                double *values, double *weights) {
     hm::clear_error();
     return hm::tridiag_ritz(k, alpha, beta, values, weights);
+}
+
+extern "C" int hm_ftl_sums(int32_t nruns, const int32_t *run_len, const double *levels,
+                           const double *weights, const double *run_scale, int32_t nT,
+                           const double *T, double *Z, double *E, double *C, double *E_min) {
+    hm::clear_error();
+    return hm::ftl_sums(nruns, run_len, levels, weights, run_scale, nT, T, Z, E, C, E_min);
 }

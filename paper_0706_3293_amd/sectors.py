@@ -13,13 +13,15 @@ values theta_j and Gauss weights |<r|y_j>|^2 (hm_tridiag_ritz), and
     Z_M ~ (D_M / R) sum_r sum_j |<r|y_j>|^2 exp(-theta_j / T)
 
 (likewise for <H> and <H^2>) with R random unit start vectors per sector;
-sectors M > 0 count twice.  The host keeps only these Boltzmann sums.
+sectors M > 0 count twice.  The Boltzmann sums run in libhm (hm_ftl_sums).
 """
+import ctypes
 from dataclasses import dataclass
 
 import numpy as np
 import torch
 
+from ._lib import check, lib
 from .api import Basis
 from .batched import BatchedProblem
 
@@ -107,17 +109,30 @@ def magnetization_curve(N: int, two_s: int, J, steps: int, nvec: int = 1, seed: 
         E0=E0_runs.min(axis=1), E0_runs=E0_runs, steps_done=done)
 
 
+def ftl_sums(levels, weights, scales, temps):
+    """Boltzmann sums of finite-temperature Lanczos (libhm's hm_ftl_sums):
+    levels[r] and weights[r] are the Ritz values and Gauss weights of run r,
+    scales[r] the factor of its weights.  Returns Z (relative to
+    exp(-E_min / T)), <H> and C = (<H^2> - <H>^2) / T^2 per temperature."""
+    lens = np.array([len(l) for l in levels], dtype=np.int32)
+    lv = np.ascontiguousarray(np.concatenate([np.asarray(l, dtype=np.float64) for l in levels]))
+    wt = np.ascontiguousarray(np.concatenate([np.asarray(w, dtype=np.float64) for w in weights]))
+    sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+    T = np.ascontiguousarray(np.asarray(temps, dtype=np.float64).ravel())
+    Z, E, C = (np.empty(len(T)) for _ in range(3))
+    emin = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().hm_ftl_sums(len(lens), lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            lv.ctypes.data_as(dp), wt.ctypes.data_as(dp), sc.ctypes.data_as(dp),
+                            len(T), T.ctypes.data_as(dp), Z.ctypes.data_as(dp),
+                            E.ctypes.data_as(dp), C.ctypes.data_as(dp), ctypes.byref(emin)))
+    return {"T": T, "E_min": emin.value, "Z": Z, "E": E, "C": C}
+
+
 def thermo_sums(levels, weights, temps):
-    """Z (relative to exp(-E_min / T)), <H> and C = (<H^2> - <H>^2) / T^2."""
-    levels = np.asarray(levels, dtype=np.float64)
-    weights = np.asarray(weights, dtype=np.float64)
-    temps = np.asarray(temps, dtype=np.float64)
-    e_min = levels.min()
-    b = np.exp(-(levels[None, :] - e_min) / temps[:, None]) * weights[None, :]
-    Z = b.sum(axis=1)
-    E = (b * levels).sum(axis=1) / Z
-    E2 = (b * levels ** 2).sum(axis=1) / Z
-    return {"T": temps, "E_min": e_min, "Z": Z, "E": E, "C": (E2 - E * E) / temps ** 2}
+    """Z (relative to exp(-E_min / T)), <H> and C = (<H^2> - <H>^2) / T^2 of
+    one list of levels with weights."""
+    return ftl_sums([levels], [weights], [1.0], temps)
 
 
 def ftl_thermodynamics(N: int, two_s: int, J, temps, steps: int, nvec: int = 16,
@@ -127,17 +142,16 @@ def ftl_thermodynamics(N: int, two_s: int, J, temps, steps: int, nvec: int = 16,
     Returns the sums of thermo_sums plus the levels and weights they came
     from and the dimension the weights add up to at T -> infinity."""
     bases, res = _run(N, two_s, J, steps, nvec, seed, V0s, tol)
-    levels, weights = [], []
+    levels, weights, scales = [], [], []
     for k, (b, tm) in enumerate(zip(bases, sector_two_M(N, two_s))):
-        scale = multiplicity(tm) * b.dim / nvec
         for r in range(nvec):
             th, w = res.ritz(k, r)
             levels.append(th)
-            weights.append(w * scale)
-    levels = np.concatenate(levels)
-    weights = np.concatenate(weights)
-    out = thermo_sums(levels, weights, temps)
-    out.update(levels=levels, weights=weights,
+            weights.append(w)
+            scales.append(multiplicity(tm) * b.dim / nvec)
+    out = ftl_sums(levels, weights, scales, temps)
+    out.update(levels=np.concatenate(levels),
+               weights=np.concatenate([w * s for w, s in zip(weights, scales)]),
                total_dim=sum(multiplicity(tm) * b.dim
                              for b, tm in zip(bases, sector_two_M(N, two_s))))
     return out

@@ -14,9 +14,38 @@ def test_thermo_sums_match_oracle():
     T = np.array([0.05, 0.3, 1.0, 7.0])
     got = thermo_sums(lev, w, T)
     want = sectors.thermo_from_levels(lev, w, T)
-    for k in ("Z", "E", "C"):
+    for k in ("Z", "E"):
         assert np.allclose(got[k], want[k], rtol=1e-12, atol=1e-14)
+    # C = (<H^2> - <H>^2) / T^2 cancels <H^2> against <H>^2: the library's
+    # compensated sums are good to about an ulp of <H^2>, numpy's pairwise
+    # sums of n terms to about log2(n) ulps, so |dC| <= (log2(n) + 4) ulps of
+    # <H^2>, divided by T^2
+    h2 = want["C"] * T ** 2 + want["E"] ** 2
+    ulps = np.log2(len(lev)) + 4
+    assert np.all(np.abs(got["C"] - want["C"]) <= ulps * np.finfo(float).eps * h2 / T ** 2)
     assert got["E_min"] == want["E_min"]
+
+
+def test_ftl_sums_run_scales_and_errors():
+    """Per-run weight scales equal pre-scaled weights of one run; bad input
+    (T <= 0, non-finite levels, zero total weight) is rejected."""
+    from paper_0706_3293_amd import _lib
+    from paper_0706_3293_amd.sectors import ftl_sums, thermo_sums
+    rng = np.random.default_rng(3)
+    runs = [rng.normal(size=n) for n in (5, 1, 12)]
+    wts = [rng.uniform(0, 1, len(r)) for r in runs]
+    scales = [3.0, 0.5, 7.0]
+    T = np.array([0.2, 1.5])
+    got = ftl_sums(runs, wts, scales, T)
+    want = thermo_sums(np.concatenate(runs), np.concatenate([w * s for w, s in zip(wts, scales)]), T)
+    for k in ("Z", "E", "C"):
+        assert np.allclose(got[k], want[k], rtol=1e-13, atol=0)
+    with pytest.raises(_lib.HMError):
+        ftl_sums(runs, wts, scales, np.array([0.0]))
+    with pytest.raises(_lib.HMError):
+        ftl_sums([np.array([np.nan])], [np.ones(1)], [1.0], T)
+    with pytest.raises(_lib.HMError):
+        ftl_sums([np.ones(3)], [np.zeros(3)], [1.0], T)
 
 
 def test_block_tridiagonal_assembly_matches_oracle():
