@@ -356,7 +356,9 @@ int hm_bond_corr_noalloc(hm_basis h, const int32_t *uv, int32_t nb,
  * solved together in FP32-mixed precision by one persistent (cooperative)
  * kernel launch that runs all steps; the multi-vector product H X shares one
  * decoding and one encoding per row among the nvec vectors.
- *   bases[k]     basis handle of instance k (any mix of N, s, M);
+ *   bases[k]     basis handle of instance k (any mix of N, s, M; states are
+ *                packed with the digit width of the largest spin in the
+ *                batch, so N_k * bits(s_max) <= 64 for every k);
  *   J[k]         host N_k x N_k coupling matrix;
  *   d_v0[k]      device FP64 array [dim_k][nvec] (row-major: the nvec start
  *                vectors interleaved, entry (i, r) at i*nvec + r);
@@ -371,7 +373,9 @@ int hm_bond_corr_noalloc(hm_basis h, const int32_t *uv, int32_t nb,
  * occupancy; 0 = 4).  Every sum has a fixed order for a given schedule, so a
  * run is reproducible; the autotuner picks the schedule per workload.
  * d_work: device workspace of at least hm_lanczos_batched_workspace bytes.
- * Synchronizes `stream`.  HM_EINVAL: bad arguments or schedule.
+ * Synchronizes `stream`.  HM_EINVAL: bad arguments or schedule.  HM_ERANGE:
+ * an instance with N_k * bits(s_max) > 64, a dimension of 2^32 or more, or a
+ * prefix table larger than the batch's LDS budget.
  * ------------------------------------------------------------------------- */
 int hm_lanczos_batched_workspace(int32_t ninst, const hm_basis *bases,
                                  int32_t nvec, int32_t steps, size_t *bytes);

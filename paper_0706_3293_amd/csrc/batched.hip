@@ -598,7 +598,7 @@ __global__ __launch_bounds__(kBatchBlock) void batched_lanczos_kernel(BatchArgs 
 struct BatchLayout {
     size_t desc, items, bar, alpha, beta, sigma, cprev, scale, norm0, stopped, partial, r0, r1,
         r2, total;
-    int n_items, NV;
+    int n_items, NV, bits;
     uint64_t rows;
 };
 
@@ -618,11 +618,19 @@ static int batch_layout(int ninst, const hm_basis *bases, int nvec, int steps, B
     L->NV = vec_width(nvec);
     L->n_items = 0;
     L->rows = 0;
+    // states of every instance are packed with the digit width of the
+    // largest spin in the batch
+    L->bits = 0;
     for (int k = 0; k < ninst; ++k) {
         if (!bases[k]) return fail(HM_EINVAL, "basis %d is null", k);
+        L->bits = std::max(L->bits, bases[k]->impl.bits);
+    }
+    for (int k = 0; k < ninst; ++k) {
         const Basis &b = bases[k]->impl;
-        if (b.two_s != bases[0]->impl.two_s)
-            return fail(HM_EINVAL, "all instances must share the spin (basis %d differs)", k);
+        if (b.N * L->bits > 64)
+            return fail(HM_ERANGE,
+                        "basis %d: %d sites at %d bits per digit (the batch's widest spin) "
+                        "exceed 64 bits", k, b.N, L->bits);
         if (!b.idx32) return fail(HM_ERANGE, "basis %d: dimension too large for the batch", k);
         if (b.prefix_len() * 4 > kBatchPrefixLds)
             return fail(HM_ERANGE, "basis %d: prefix table exceeds the batch LDS budget", k);
@@ -783,7 +791,7 @@ int hm_lanczos_batched(int32_t ninst, const hm_basis *bases, const double *const
     const size_t lds = ((size_t)(max_prefix * 4 + 15) / 16) * 16 + 32 * sizeof(double) +
                        (size_t)hm::kStageWaves * L.NV * sizeof(double) +
                        (size_t)max_bonds * sizeof(hm::LdsBond);
-    const int bits = bases[0]->impl.bits;
+    const int bits = L.bits;
     int grid = 0, rc;
     switch (L.NV) {
         case 1: rc = hm::dispatch_bits<1>(bits, a, lds, wg_per_cu, st, &grid); break;

@@ -127,14 +127,46 @@ def test_batched_breakdown_and_padding():
 def test_batched_rejects_bad_input():
     from paper_0706_3293_amd import Basis, _lib, lanczos_batched
     b1 = Basis(4, two_s=1, two_M=0)
-    b2 = Basis(3, two_s=2, two_M=0)
-    J4, J3 = np.zeros((4, 4)), np.zeros((3, 3))
+    J4 = np.zeros((4, 4))
     J4[0, 1] = J4[1, 0] = 1.0
-    J3[0, 1] = J3[1, 0] = 1.0
-    with pytest.raises(_lib.HMError):
-        lanczos_batched([b1, b2], [J4, J3], [np.ones((2, b1.dim)), np.ones((2, b2.dim))], 5)
     with pytest.raises(_lib.HMError):
         lanczos_batched([b1], [J4], [np.zeros((2, b1.dim))], 5)
+    # 40 sites of spin 1/2 fit one 64-bit word alone, but not at the 2 bits
+    # per digit that a spin-1 instance in the same batch needs
+    b40 = Basis(40, two_s=1, two_M=36)
+    b3 = Basis(3, two_s=2, two_M=0)
+    J40 = np.zeros((40, 40))
+    J40[0, 1] = J40[1, 0] = 1.0
+    J3 = np.zeros((3, 3))
+    J3[0, 1] = J3[1, 0] = 1.0
+    with pytest.raises(_lib.HMError, match="64 bits"):
+        lanczos_batched([b40, b3], [J40, J3], [np.ones((2, b40.dim)), np.ones((2, b3.dim))], 5)
+
+
+def test_batched_mixed_spins_vs_oracle():
+    """Instances of spin 1/2, 1, 3/2 and 7/2 in one launch (digits packed at
+    the widest spin's 3 bits) against the oracle's FP64 recurrence: E0 within
+    1e-7 relative on converged runs, first coefficients at the FP32 level."""
+    import oracle
+    from paper_0706_3293_amd import Basis, lanczos_batched
+    rng = np.random.default_rng(7)
+    specs = [(12, 1, 6), (8, 2, 8), (6, 3, 9), (4, 7, 14), (11, 1, 4)]   # (N, 2s, A)
+    bases, Js, V0s = [], [], []
+    for N, two_s, A in specs:
+        b = Basis(N, two_s=two_s, two_M=N * two_s - 2 * A)
+        bases.append(b)
+        Js.append(_rand_J(N, rng))
+        V0s.append(rng.uniform(-1, 1, (4, b.dim)))
+    steps = 120
+    res = lanczos_batched(bases, Js, V0s, steps)
+    for k, (N, two_s, A) in enumerate(specs):
+        sub = oracle.Subspace(N, two_s, A)
+        for r in range(4):
+            ref = oracle.lanczos(sub, Js[k], V0s[k][r], steps)
+            assert res.steps_done[k, r] == ref["steps_done"], (k, r)
+            assert np.abs(res.alpha[k, r, :5] - ref["alpha"][:5]).max() <= \
+                2e-6 * np.abs(ref["alpha"][:5]).max()
+            assert abs(res.E0[k, r] - ref["E0"]) <= 1e-7 * abs(ref["E0"]), (k, r)
 
 
 def test_batched_full_workload_vs_f64():
@@ -166,7 +198,7 @@ def test_batched_spin_one_and_three_halves_vs_oracle(nvec):
     import oracle
     from paper_0706_3293_amd import Basis, lanczos_batched
     rng = np.random.default_rng(100 + nvec)
-    # one launch per spin (the instances of a launch share it); (N, 2s, A)
+    # one launch per spin; (N, 2s, A)
     for specs in ([(8, 2, 8), (7, 2, 5), (9, 2, 7)], [(6, 3, 9), (5, 3, 6)]):
         bases, Js, V0s = [], [], []
         for N, two_s, A in specs:
