@@ -130,10 +130,19 @@ if cfg["full_runs"]:
     v20 = np.random.default_rng(0).uniform(-1.0, 1.0, s20.dim)
     t0 = time.perf_counter(); s20.apply(J20, v20)
     out["all_to_all20_hx_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.lanczos(s20, J20, v20, 3)
+    out["all_to_all20_s_per_step"] = (time.perf_counter() - t0) / 3
     Jp = np.array(cfg["Jp"]); sp = oracle.Subspace(20, 2, 7)
     vp = np.random.default_rng(0).uniform(-1.0, 1.0, sp.dim)
     t0 = time.perf_counter(); oracle.lanczos(sp, Jp, vp, 10)
     out["paper_vector_length_s_per_step"] = (time.perf_counter() - t0) / 10
+    # the N=28 J1-J2 ring (dim 40,116,600): one full H x and one step
+    J28 = np.array(cfg["J28"]); s28 = oracle.Subspace(28, 1, 14)
+    v28 = np.random.default_rng(0).uniform(-1.0, 1.0, s28.dim)
+    t0 = time.perf_counter(); s28.apply(J28, v28)
+    out["j1j2_ring28_hx_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter(); oracle.lanczos(s28, J28, v28, 1)
+    out["j1j2_ring28_step_s"] = time.perf_counter() - t0
 print(json.dumps(out))
 """
 
@@ -144,7 +153,8 @@ def oracle_child(N, J, rows, threads, full_runs):
     cfg = dict(root=ROOT, N=N, J=np.asarray(J).tolist(), rows=rows, full_runs=full_runs,
                J12=inputs.ring_couplings(12, -1.0).tolist(),
                J20=inputs.all_to_all_couplings(20, 0)[0].tolist(),
-               Jp=inputs.ring_couplings(20, -1.0).tolist())
+               Jp=inputs.ring_couplings(20, -1.0).tolist(),
+               J28=inputs.workload_couplings("j1j2_ring28").tolist())
     env = dict(os.environ)
     if threads:
         env["OMP_NUM_THREADS"] = str(threads)
