@@ -65,6 +65,11 @@ def parse():
     ap.add_argument("--extras-only", action="store_true",
                     help="only time the other workloads (a profiling mode: prints "
                          "{\"other_workloads\": ...}, not the benchmark line)")
+    ap.add_argument("--extras-select", default=None,
+                    help="comma-separated names of the other workloads to run "
+                         "(j1j2_ring28, ring12, all_to_all20, spin1_chains_batched, "
+                         "sectors, hx_design_ablations, block_lanczos_ring24, "
+                         "paper_vector_length_484500, hx_ring36_f32); default all")
     return ap.parse_args()
 
 
@@ -185,12 +190,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def extras():
-    """Timings of the other measured workloads (one GPU, inputs resident)."""
+def _extra_j1j2_ring28(out):
     import torch
 
-    from paper_0706_3293_amd import (Basis, BatchedProblem, ground_state_energy, inputs)
-    out = {}
+    from paper_0706_3293_amd import Basis, inputs
     # the N=28 J1-J2 ring at the Majumdar-Ghosh point (dim 40,116,600): 200
     # Lanczos steps in each precision with the schedules stored for it, E0
     # against the exact -3N/8
@@ -213,6 +216,12 @@ def extras():
     r28["mixed_over_f64_step_speedup"] = r28["f64"]["ms_per_step"] / r28["f32_mixed"]["ms_per_step"]
     out["j1j2_ring28"] = r28
     torch.cuda.empty_cache()
+
+
+def _extra_ring12(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, inputs
     # N=12 ring, 120 steps with full reorthogonalization, FP64
     b = Basis(12, two_s=1, two_M=0)
     J = inputs.ring_couplings(12, -1.0)
@@ -229,25 +238,54 @@ def extras():
             best = min(best, time.perf_counter() - t0)
         out["ring12"][name + "_ms"] = 1e3 * best
         out["ring12"][name + "_E0"] = res.E0
-    # N=20 all-to-all: E0(J) forward (300 steps FP64) and gradient of 190 bonds
-    b = Basis(20, two_s=1, two_M=0)
+
+
+def _extra_all_to_all20(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, autotune, ground_state_energy, inputs
+    # N=20 all-to-all: E0(J) forward (300 steps FP64) and gradient of 190
+    # bonds, on the block kernel in its default schedule and in the one the
+    # autotuner picks for these couplings (FP64)
     J, bonds, vals = inputs.all_to_all_couplings(20, 0)
-    v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
-    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
-    ground_state_energy(Jv, b, bonds, v0, 300).backward()          # warm
-    Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
-    t0 = time.perf_counter()
-    E0 = ground_state_energy(Jv, b, bonds, v0, 300)
-    t1 = time.perf_counter()
-    E0.backward()
-    t2 = time.perf_counter()
+    tuned = autotune.tune(20, J, dtype=torch.float64, reps=20, cache=None)
+    runs = {}
+    for label, sched in (("default", None), ("tuned", tuned)):
+        b = Basis(20, two_s=1, two_M=0)
+        if sched is not None:
+            b.set_schedule(*sched)
+        v0 = torch.tensor(inputs.start_vector(b.dim, 0), device="cuda")
+        Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+        ground_state_energy(Jv, b, bonds, v0, 300).backward()      # warm
+        best = None
+        for _ in range(3):                      # best of three (short runs)
+            Jv = torch.tensor(vals, dtype=torch.float64, requires_grad=True)
+            t0 = time.perf_counter()
+            E0 = ground_state_energy(Jv, b, bonds, v0, 300)
+            t1 = time.perf_counter()
+            E0.backward()
+            t2 = time.perf_counter()
+            if best is None or t2 - t0 < best[2] - best[0]:
+                best = (t0, t1, t2, E0, Jv)
+        runs[label] = best
+        dim = b.dim
+    t0, t1, t2, E0, Jv = runs["tuned"]
+    d0, d1, d2 = runs["default"][:3]
     # bond evaluations: every row tests every bond once per H x (300 forward
     # steps; the backward repeats them and adds one pass over all bonds)
-    bond_evals = 300 * b.dim * len(bonds)
+    bond_evals = 300 * dim * len(bonds)
     out["all_to_all20"] = dict(forward_ms=1e3 * (t1 - t0), backward_ms=1e3 * (t2 - t1),
+                               schedule=list(tuned), forward_ms_default_schedule=1e3 * (d1 - d0),
+                               backward_ms_default_schedule=1e3 * (d2 - d1),
                                steps=300, bonds=len(bonds), E0=float(E0.detach()),
                                forward_bond_evals_per_s=bond_evals / (t1 - t0),
                                euler_residual=abs(float(np.dot(vals, Jv.grad.numpy())) - float(E0)))
+
+
+def _extra_spin1_chains_batched(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, BatchedProblem, inputs
     # 64 spin-1 chains x 16 start vectors x 80 steps, one persistent launch,
     # in the default schedule and in the one the autotuner picks
     from paper_0706_3293_amd import autotune
@@ -279,6 +317,12 @@ def extras():
         hbm_frac_default_schedule=alg / runs["default"][0] / 1e9 / HBM_PEAK_GBS,
         E0_spread_max=float(np.max(np.ptp(r.E0, axis=1))))
     del prob
+
+
+def _extra_sectors(out):
+    import torch
+
+    from paper_0706_3293_amd import inputs
     # magnetization curve of the N=24 J1-J2 ring: 13 sectors M >= 0, 2 start
     # vectors each, 150 steps (one Lanczos run per sector and vector on the
     # block kernel, and the batched path for comparison); then finite-
@@ -306,6 +350,12 @@ def extras():
     dt = time.perf_counter() - t0
     out["ftl_ring20"] = dict(ms=1e3 * dt, sectors=11, vectors=16, steps=60, T=temps,
                              E=[float(e) for e in th["E"]], C=[float(x) for x in th["C"]])
+
+
+def _extra_hx_design_ablations(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, inputs
     # the paper's design alternatives for H x, FP32, ms per apply: 1 generic
     # row gather (decode every row), 2 spin-1/2 block kernel, 3 successor
     # sweep (decode one row in 16), 4 column scatter with atomic adds
@@ -330,6 +380,12 @@ def extras():
         abl[name] = t
         del x, y
     out["hx_design_ablations"] = abl
+
+
+def _extra_block_lanczos_ring24(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, inputs
     # block Lanczos: the 4 lowest levels of the N=24 J1-J2 ring at M=0 (dim
     # 2,704,156), p = 4, 60 block steps with full reorthogonalization, FP64
     b = Basis(24, two_s=1, two_M=0)
@@ -341,6 +397,12 @@ def extras():
     dt = time.perf_counter() - t0
     out["block_lanczos_ring24"] = dict(ms=1e3 * dt, dim=b.dim, p=4, steps=60,
                                        levels=[float(e) for e in lev])
+
+
+def _extra_paper_vector_length_484500(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, inputs
     # the vector length of the paper's only timing experiment (200 Lanczos
     # iterations, length 484,500 = D(N=20, s=1, M=13); the system is not
     # named, so an N=20 spin-1 ring stands in), FP64
@@ -356,6 +418,12 @@ def extras():
         dt = min(dt, time.perf_counter() - t0)
     out["paper_vector_length_484500"] = dict(ms=1e3 * dt, dim=b.dim, steps=200,
                                              ms_per_step=1e3 * dt / 200, E0=res.E0)
+
+
+def _extra_hx_ring36_f32(out):
+    import torch
+
+    from paper_0706_3293_amd import Basis, inputs
     # the largest size: N=36 J1-J2 ring at M=0 (dim 9,075,135,300 > 2^32, 64-bit
     # indices), one FP32 H x on the block kernel, 36 GB per vector
     b = Basis(36, two_s=1, two_M=0)
@@ -378,6 +446,30 @@ def extras():
                                 alg_gbs=8 * b.dim / (ms * 1e-3) / 1e9)
     del x, y
     torch.cuda.empty_cache()
+
+
+EXTRAS = (
+    ("j1j2_ring28", _extra_j1j2_ring28),
+    ("ring12", _extra_ring12),
+    ("all_to_all20", _extra_all_to_all20),
+    ("spin1_chains_batched", _extra_spin1_chains_batched),
+    ("sectors", _extra_sectors),
+    ("hx_design_ablations", _extra_hx_design_ablations),
+    ("block_lanczos_ring24", _extra_block_lanczos_ring24),
+    ("paper_vector_length_484500", _extra_paper_vector_length_484500),
+    ("hx_ring36_f32", _extra_hx_ring36_f32),
+)
+
+
+def extras(select=None):
+    """Timings of the other measured workloads (one GPU, inputs resident);
+    select: names of EXTRAS to run (all when None)."""
+    import torch
+    out = {}
+    for name, fn in EXTRAS:
+        if select is None or name in select:
+            fn(out)
+            torch.cuda.empty_cache()
     return out
 
 
@@ -414,6 +506,11 @@ def load_golden(workload):
 
 def main():
     args = parse()
+    select = set(args.extras_select.split(",")) if args.extras_select else None
+    if select is not None and not select <= {n for n, _ in EXTRAS}:
+        print(f"unknown --extras-select names: {sorted(select - {n for n, _ in EXTRAS})}",
+              file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "multi-GPU sharding of this path is described, not built.", file=sys.stderr)
@@ -424,7 +521,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.extras_only:
-        print(json.dumps({"other_workloads": extras()}), flush=True)
+        print(json.dumps({"other_workloads": extras(select)}), flush=True)
         return
     w = inputs.WORKLOADS[args.workload]
     N = w["N"]
@@ -524,7 +621,7 @@ def main():
 
     other = None
     if not args.no_extras:
-        other = extras()
+        other = extras(select)
         log(f"other workloads: {json.dumps(other)}")
 
     cpu = cpu_detail = None
