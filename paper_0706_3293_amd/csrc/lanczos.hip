@@ -185,6 +185,11 @@ __global__ __launch_bounds__(kBlock) void finish_alpha(LzDev *lz, const double *
     if (threadIdx.x == 0) alpha[k] = s;
 }
 
+// 16-byte vector type of an element type.
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using type = float4; };
+template <> struct VecOf<double> { using type = double2; };
+
 // w -= alpha_k sigma_k r_k (FP64 arithmetic, one rounding), partial |w|^2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pass_b(T *__restrict__ w, const T *__restrict__ r,
@@ -197,8 +202,34 @@ __global__ __launch_bounds__(kBlock) void pass_b(T *__restrict__ w, const T *__r
     const double a = alpha[k] * sigma[k];
     int64_t first, last;
     block_rows<int64_t>(xcd_logical_block(blockIdx.x, gridDim.x), gridDim.x, n, first, last);
+    // 16-byte vector loads and stores over the aligned middle of the range
+    // (the buffers start on 256-byte boundaries), single elements at its ends
+    constexpr int V = 16 / sizeof(T);
+    using Vec = typename VecOf<T>::type;
+    const int64_t m0 = std::min(last, (first + V - 1) / V * V);
+    const int64_t m1 = std::max(m0, last / V * V);
     double s = 0.0;
-    for (int64_t i = first + threadIdx.x; i < last; i += blockDim.x) {
+    for (int64_t i = first + threadIdx.x; i < m0; i += blockDim.x) {
+        const T wi = (T)((double)w[i] - a * (double)r[i]);
+        w[i] = wi;
+        s += (double)wi * (double)wi;
+    }
+    Vec *wv = reinterpret_cast<Vec *>(w);
+    const Vec *rv = reinterpret_cast<const Vec *>(r);
+#pragma unroll 2
+    for (int64_t j = m0 / V + threadIdx.x; j < m1 / V; j += blockDim.x) {
+        Vec wj = wv[j];
+        const Vec rj = rv[j];
+        T *we = reinterpret_cast<T *>(&wj);
+        const T *re = reinterpret_cast<const T *>(&rj);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            we[e] = (T)((double)we[e] - a * (double)re[e]);
+            s += (double)we[e] * (double)we[e];
+        }
+        wv[j] = wj;
+    }
+    for (int64_t i = m1 + threadIdx.x; i < last; i += blockDim.x) {
         const T wi = (T)((double)w[i] - a * (double)r[i]);
         w[i] = wi;
         s += (double)wi * (double)wi;
