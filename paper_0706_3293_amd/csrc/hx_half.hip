@@ -26,8 +26,8 @@
 // shift = -sum_b J_b / 4 (s = 1/2: m_u m_v = +-1/4 and every allowed ladder
 // term has matrix element -J/2).  A bond that cannot flip gathers x_i itself
 // and so adds zero; this keeps eight gathers in flight without branches.
-// Each row is written by one lane; workgroups are persistent and each XCD
-// sweeps one contiguous slice of the items.
+// Each row is written by one lane; workgroups are persistent, and the eight
+// XCDs take turns on runs of consecutive items so that they sweep x together.
 #include <algorithm>
 #include <vector>
 
@@ -41,6 +41,18 @@ constexpr int kHalfMaxHighBits = 24;
 constexpr int kGroup = 8;
 constexpr uint32_t kNoHigh = 0xFFFFFFFFu;      // padding slot of a high-word group
 constexpr size_t kMaxNeighbourBytes = (size_t)4 << 30;
+
+// Persistent sweep over the items (grid a multiple of 8; workgroup b runs on
+// XCD b % 8): the XCDs take turns on runs of kSweepRun consecutive items, so
+// all eight work in the same region of x at any time and gathers that reach
+// far share the Infinity Cache, while a run keeps neighbouring blocks within
+// one XCD's L2.  Local index l of XCD x8 (its waves stride through l
+// together) maps to item (l / run) * 8 run + x8 run + l % run.
+constexpr uint32_t kSweepRun = 64;
+
+__device__ __forceinline__ uint32_t sweep_item(uint32_t l, uint32_t x8) {
+    return (l / kSweepRun) * (kXcds * kSweepRun) + x8 * kSweepRun + l % kSweepRun;
+}
 
 // Eight bonds of one group, structure-of-arrays so one group is fetched with
 // a few wide scalar loads.
@@ -140,28 +152,25 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
     const T shift = (T)g.shift;
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    // Item range of this wave: with a grid that is a multiple of 8, XCD
-    // (blockIdx % 8) owns the contiguous eighth [x n/8, (x+1) n/8) of the items
-    // and its waves stride through it together.
-    uint32_t first = 0, last = g.n_items, stride = gridDim.x * nw, wl;
-    if (gridDim.x % kXcds == 0) {
-        const uint32_t x8 = blockIdx.x % kXcds, per = gridDim.x / kXcds;
-        first = (uint32_t)((uint64_t)g.n_items * x8 / kXcds);
-        last = (uint32_t)((uint64_t)g.n_items * (x8 + 1) / kXcds);
-        stride = per * nw;
+    uint32_t stride = gridDim.x * nw, wl, x8 = 0;
+    const bool by_xcd = gridDim.x % kXcds == 0;
+    if (by_xcd) {
+        x8 = blockIdx.x % kXcds;
+        stride = (gridDim.x / kXcds) * nw;
         wl = (blockIdx.x / kXcds) * nw + (threadIdx.x >> 6);
     } else {
         wl = blockIdx.x * nw + (threadIdx.x >> 6);
     }
     wl = __builtin_amdgcn_readfirstlane(wl);
-    first = __builtin_amdgcn_readfirstlane(first);
-    last = __builtin_amdgcn_readfirstlane(last);
+    x8 = __builtin_amdgcn_readfirstlane(x8);
     stride = __builtin_amdgcn_readfirstlane(stride);
     const BondGroup *__restrict__ gl = g.groups;
     const BondGroup *__restrict__ gh = g.groups + g.nLg;
     const BondGroup *__restrict__ gs = g.groups + g.nLg + g.nHg;
     double dot = 0.0;
-    for (uint32_t it = first + wl; it < last; it += stride) {
+    for (uint32_t l = wl;; l += stride) {
+        const uint32_t it = by_xcd ? sweep_item(l, x8) : l;
+        if (it >= g.n_items) break;
         const uint32_t item = g.items[it];
         const uint32_t *__restrict__ hg = g.hgroups + (size_t)(item >> 8) * R;
         uint32_t hs[R];
@@ -486,24 +495,24 @@ __global__ __launch_bounds__(256) void hx_half_staged_kernel(
     w.shift = (T)g.shift;
     w.lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    uint32_t first = 0, last = g.n_items, stride = gridDim.x * nw, wl;
-    if (gridDim.x % kXcds == 0) {
-        const uint32_t x8 = blockIdx.x % kXcds, per = gridDim.x / kXcds;
-        first = (uint32_t)((uint64_t)g.n_items * x8 / kXcds);
-        last = (uint32_t)((uint64_t)g.n_items * (x8 + 1) / kXcds);
-        stride = per * nw;
+    uint32_t stride = gridDim.x * nw, wl, x8 = 0;
+    const bool by_xcd = gridDim.x % kXcds == 0;
+    if (by_xcd) {
+        x8 = blockIdx.x % kXcds;
+        stride = (gridDim.x / kXcds) * nw;
         wl = (blockIdx.x / kXcds) * nw + (threadIdx.x >> 6);
     } else {
         wl = blockIdx.x * nw + (threadIdx.x >> 6);
     }
     wl = __builtin_amdgcn_readfirstlane(wl);
-    first = __builtin_amdgcn_readfirstlane(first);
-    last = __builtin_amdgcn_readfirstlane(last);
+    x8 = __builtin_amdgcn_readfirstlane(x8);
     stride = __builtin_amdgcn_readfirstlane(stride);
     const Const<uint32_t> *hgroups = as_const(g.hgroups);
     const Const<I> *offs = as_const(g.off);
     double dot = 0.0;
-    for (uint32_t it = first + wl; it < last; it += stride) {
+    for (uint32_t l = wl;; l += stride) {
+        const uint32_t it = by_xcd ? sweep_item(l, x8) : l;
+        if (it >= g.n_items) break;
         const Const<uint32_t> *hg = hgroups + (size_t)it * R;
         uint32_t hs[R];
         bool valid[R];
