@@ -115,6 +115,17 @@ int hm_basis_info(hm_basis h, int32_t *N, int32_t *two_s, int32_t *A,
 int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
                           int32_t rows_per_lane);
 
+/* Grid of the spin-1/2 block kernel: about items_per_wave work items per
+ * wave (a work item is R blocks in the staged split, or R blocks' 64-row chunk
+ * in the chunked one), so the grid may exceed the workgroups that are resident
+ * at once and the hardware dispatcher balances items of unequal size; at most
+ * 2^20 workgroups.  0 keeps the default: one item per wave up to 2048
+ * workgroups, which then take several items each.  The Lanczos workspace
+ * grows by one FP64 partial sum per workgroup.  Must be called before the
+ * first device use of the handle.  Used by the autotuner.
+ * HM_EINVAL: items_per_wave outside 0..65536, or tables already built. */
+int hm_basis_set_items_per_wave(hm_basis h, int32_t items_per_wave);
+
 /* Work split of the spin-1/2 block kernel: 1 = items of 64 rows of a block
  * (the low-word gathers read global memory); 2 = staged blocks: one wave takes
  * all rows of its R blocks, copies them to LDS and serves the gathers of the

@@ -65,6 +65,7 @@ SIGNATURES = {
     "hm_tridiag_lowest": (_i32, [_i32, _dblp, _dblp, _dblp, _dblp]),
     "hm_tridiag_ritz": (_i32, [_i32, _dblp, _dblp, _dblp, _dblp]),
     "hm_block_tridiag_eigenvalues": (_i32, [_i32, _i32, _dblp, _dblp, _dblp]),
+    "hm_basis_set_items_per_wave": (_i32, [_vp, _i32]),
     "hm_ftl_sums": (_i32, [_i32, _i32p, _dblp, _dblp, _dblp, _i32, _dblp, _dblp, _dblp,
                             _dblp, _dblp]),
     "hm_block_lanczos_workspace": (_i32, [_vp, _i32, _i32, _szp]),

@@ -135,12 +135,14 @@ class Basis:
         return self._h
 
     def set_schedule(self, low_bits: int = 0, block_threads: int = 0, rows_per_lane: int = 0,
-                     staging: int = 0):
+                     staging: int = 0, items_per_wave: int = 0):
         """Schedule of the spin-1/2 block kernel (before first device use);
-        staging: 0 automatic, 1 chunked items, 2 staged blocks."""
+        staging: 0 automatic, 1 chunked items, 2 staged blocks; items_per_wave
+        sizes the grid (0: the default grid)."""
         check(lib().hm_basis_set_schedule(self._h, int(low_bits), int(block_threads),
                                           int(rows_per_lane)))
         check(lib().hm_basis_set_staging(self._h, int(staging)))
+        check(lib().hm_basis_set_items_per_wave(self._h, int(items_per_wave)))
 
     # --- codec ------------------------------------------------------------
     def unrank(self, i: int) -> np.ndarray:

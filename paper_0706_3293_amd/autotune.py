@@ -4,7 +4,9 @@ persistent Lanczos launch.
 For a given problem (N, M, couplings, element type) every candidate schedule
 (low bits K, workgroup size, rows per lane, work split) is built on a fresh basis handle
 and timed with HIP events over a few H x applications on the current stream;
-the fastest is returned and remembered in a JSON cache keyed by the problem.
+then the grid of the fastest is tuned (work items per wave, 0 for the default
+grid).  The result, a 5-tuple, is remembered in a JSON cache keyed by the
+problem.
 A chosen schedule is fixed for the lifetime of its basis handle, so the two
 Lanczos passes of the gradient (which must agree bit for bit) always run the
 same kernel configuration.
@@ -23,6 +25,9 @@ DEFAULT_CACHE = os.environ.get(
 
 
 TIE = 0.01      # relative timing difference treated as a tie
+# work items per wave tried for the grid of the fastest schedule (0: the
+# default grid, listed first so that near-ties keep it)
+IPW_CANDIDATES = (0, 4, 8, 16, 32, 64)
 
 
 def candidates(N):
@@ -70,8 +75,9 @@ def time_apply(b, J, x, y, reps):
 
 
 def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbose=False):
-    """Best (K, block, R, staging) for H x with these couplings; results are
-    cached (entries of an older three-field format are tuned again)."""
+    """Best (K, block, R, staging, items per wave) for H x with these
+    couplings; results are cached (entries of older, shorter formats are
+    tuned again)."""
     key = _key(N, two_M, J, str(dtype))
     table = {}
     if cache and os.path.exists(cache):
@@ -80,7 +86,7 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
                 table = json.load(f)
         except (OSError, ValueError):
             table = {}
-    if key in table and len(table[key]["schedule"]) == 4:
+    if key in table and len(table[key]["schedule"]) == 5:
         return tuple(table[key]["schedule"])
     probe = Basis(N, two_s=1, two_M=two_M)
     x = torch.rand(probe.dim, dtype=dtype, device="cuda")
@@ -99,7 +105,20 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
     # the first candidate (in the order above) within TIE of the fastest, so
     # that near-ties do not flip the choice from one run to the next
     fastest = min(ms for _, ms in trials)
-    best, best_ms = next((s, ms) for s, ms in trials if ms <= (1.0 + TIE) * fastest)
+    best4 = next(s for s, ms in trials if ms <= (1.0 + TIE) * fastest)
+    # second stage: the grid of that schedule
+    for ipw in IPW_CANDIDATES:
+        sched = tuple(best4) + (ipw,)
+        b = Basis(N, two_s=1, two_M=two_M)
+        b.set_schedule(*sched)
+        ms = time_apply(b, J, x, y, reps)
+        trials.append((sched, ms))
+        if verbose:
+            print(f"[autotune] {best4} items/wave={ipw}: {ms:.3f} ms", flush=True)
+        del b
+    staged2 = [(s, ms) for s, ms in trials if len(s) == 5]
+    fastest = min(ms for _, ms in staged2)
+    best, best_ms = next((s, ms) for s, ms in staged2 if ms <= (1.0 + TIE) * fastest)
     if cache:
         table[key] = {"schedule": list(best), "ms": best_ms,
                       "trials": [[list(s), m] for s, m in trials]}

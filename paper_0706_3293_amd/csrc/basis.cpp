@@ -319,6 +319,19 @@ int hm_basis_set_schedule(hm_basis h, int32_t low_bits, int32_t block_threads,
     return HM_OK;
 }
 
+int hm_basis_set_items_per_wave(hm_basis h, int32_t items_per_wave) {
+    hm::clear_error();
+    if (!h) return fail(HM_EINVAL, "null handle");
+    hm::Basis &b = h->impl;
+    std::lock_guard<std::mutex> lock(b.mu);
+    if (b.half_tables)
+        return fail(HM_EINVAL, "items per wave must be set before the first device use");
+    if (items_per_wave < 0 || items_per_wave > (1 << 16))
+        return fail(HM_EINVAL, "items per wave %d outside 0..65536", items_per_wave);
+    b.half_ipw = items_per_wave;
+    return HM_OK;
+}
+
 int hm_basis_set_staging(hm_basis h, int32_t mode) {
     hm::clear_error();
     if (!h) return fail(HM_EINVAL, "null handle");

@@ -108,6 +108,7 @@ struct Basis {
     int half_block = 0;      // threads per workgroup (64, 128 or 256)
     int half_R = 0;          // rows per lane (high words sharing one low word)
     int half_staging = 0;    // 0 automatic, 1 chunked items, 2 staged blocks
+    int half_ipw = 0;        // work items per wave that size the grid (0: default grid)
     void *half_tables = nullptr;
     void (*half_tables_free)(void *) = nullptr;
     // instantiated graphs of Lanczos step loops, most recently used first,

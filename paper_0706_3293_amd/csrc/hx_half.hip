@@ -41,6 +41,7 @@ constexpr int kHalfMaxHighBits = 24;
 constexpr int kGroup = 8;
 constexpr uint32_t kNoHigh = 0xFFFFFFFFu;      // padding slot of a high-word group
 constexpr size_t kMaxNeighbourBytes = (size_t)4 << 30;
+constexpr int64_t kMaxHalfGrid = 1 << 20;   // workgroups (and FP64 partials) of one launch
 
 // Persistent sweep over the items (grid a multiple of 8; workgroup b runs on
 // XCD b % 8): the XCDs take turns on runs of kSweepRun consecutive items, so
@@ -71,6 +72,7 @@ struct BondGroup {
 // Per-basis tables of the block kernel.
 struct HalfTables {
     int K = 0, block = 256, R = 1, C = 0;   // C > 0: staged blocks of 64 C entries
+    int ipw = 0;                            // items per wave that size the grid (0: default)
     int64_t n_items = 0, n_groups = 0;
     std::vector<uint64_t> off_host;
     uint16_t *d_rankL = nullptr, *d_unrankL = nullptr;
@@ -620,10 +622,21 @@ static int64_t group_count(const Basis *b) {
     return n;
 }
 
-static int grid_for_items(int64_t n_items, int block) {
+// Workgroups for n_items work items: by default one item per wave up to
+// kMaxGrid workgroups (then the persistent waves take several each); with
+// ipw > 0 about ipw items per wave, up to kMaxHalfGrid workgroups.  A grid
+// larger than the resident workgroups leaves the balancing of unequal items
+// (blocks of 1 to 252 rows in the staged split) to the hardware dispatcher.
+static int grid_for_items(int64_t n_items, int block, int ipw) {
     const int nw = block / 64;
-    int64_t g = (n_items + nw - 1) / nw;
-    g = std::min<int64_t>(g, kMaxGrid);
+    int64_t g;
+    if (ipw > 0) {
+        g = (n_items + (int64_t)nw * ipw - 1) / ((int64_t)nw * ipw);
+        g = std::min<int64_t>(g, kMaxHalfGrid);
+    } else {
+        g = (n_items + nw - 1) / nw;
+        g = std::min<int64_t>(g, kMaxGrid);
+    }
     g = std::max<int64_t>(g, 1);
     if (g >= kXcds) g -= g % kXcds;
     return (int)g;
@@ -631,7 +644,7 @@ static int grid_for_items(int64_t n_items, int block) {
 
 // Workgroups of the block kernel (= FP64 partial sums it writes).
 int hx_half_grid(const Basis *b) {
-    return grid_for_items(staged_of(b) ? group_count(b) : item_count(b), block_of(b));
+    return grid_for_items(staged_of(b) ? group_count(b) : item_count(b), block_of(b), b->half_ipw);
 }
 
 static hipError_t upload(void **dst, const void *src, size_t bytes) {
@@ -660,6 +673,7 @@ static int half_prepare(Basis *b, HalfTables **out) {
     t->R = R;
     t->block = block_of(b);
     t->C = staged_of(b) ? staged_entries(K) : 0;
+    t->ipw = b->half_ipw;
     const int nlow = 1 << K;
     std::vector<uint16_t> rankL(nlow), unrankL(nlow);
     std::vector<int> fill(K + 1, 0);
@@ -867,7 +881,7 @@ static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
 
 template <typename T, typename I, int R>
 static void launch_r(const HalfTables *t, const HalfArgs<I> &g, const HxPass &p, hipStream_t st) {
-    const int grid = grid_for_items(t->n_items, t->block);
+    const int grid = grid_for_items(t->n_items, t->block, t->ipw);
     const size_t lds = 2 * sizeof(uint16_t) * ((size_t)1 << t->K);
     const T *x = (const T *)p.x;
     T *y = (T *)p.y;
@@ -887,7 +901,7 @@ static void launch_r(const HalfTables *t, const HalfArgs<I> &g, const HxPass &p,
 template <typename T, int R, int C>
 static void launch_staged(const HalfTables *t, const HalfArgs<uint32_t> &g, const HxPass &p,
                           hipStream_t st) {
-    const int grid = grid_for_items(t->n_groups, t->block);
+    const int grid = grid_for_items(t->n_groups, t->block, t->ipw);
     const size_t lds = 2 * sizeof(uint16_t) * ((size_t)1 << t->K) +
                        (size_t)(t->block / 64) * R * 64 * C * sizeof(T);
     const T *x = (const T *)p.x;

@@ -88,13 +88,14 @@ static int vec_grid(int64_t n) {
     return (int)g;
 }
 
-// Workspace layout; the partial-sum area holds kMaxGrid entries, enough for
-// any H x kernel, so the layout does not depend on the kernel choice.
+// Workspace layout; the partial-sum area holds one entry per workgroup of
+// whichever H x kernel may run (kMaxGrid, or the block kernel's grid when its
+// schedule asks for more), so the layout does not depend on the kernel choice.
 static Layout layout(const Basis *b, int steps, int prec, int reorth) {
     Layout L{};
     const size_t es = prec == HM_PREC_F64 ? 8 : 4;
     L.grid_vec = vec_grid(b->dim);
-    L.nparts = kMaxGrid;
+    L.nparts = std::max(kMaxGrid, half_supported(b) ? hx_half_grid(b) : 0);
     size_t partial_len = (size_t)L.nparts;
     if (reorth) partial_len = std::max(partial_len, (size_t)L.grid_vec * (size_t)steps);
     size_t off = 0;

@@ -106,6 +106,11 @@ def test_error_paths(L):
     assert L.hm_basis_set_staging(None, 1) == _lib.HM_EINVAL
     for mode in (0, 1, 2):
         assert L.hm_basis_set_staging(h.handle, mode) == _lib.HM_OK
+    for ipw in (-1, 65537):
+        assert L.hm_basis_set_items_per_wave(h.handle, ipw) == _lib.HM_EINVAL
+    assert L.hm_basis_set_items_per_wave(None, 4) == _lib.HM_EINVAL
+    for ipw in (0, 1, 64, 65536):
+        assert L.hm_basis_set_items_per_wave(h.handle, ipw) == _lib.HM_OK
     out = ctypes.c_int64()
     assert L.hm_count(3, 0, 0, ctypes.byref(out)) == _lib.HM_EINVAL
     assert L.hm_count(3, 1, 0, None) == _lib.HM_EINVAL

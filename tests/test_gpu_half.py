@@ -244,7 +244,8 @@ def test_autotuner_picks_a_valid_schedule(tmp_path):
     J = inputs.ring_couplings(N, -1.0, -0.3)
     cache = str(tmp_path / "tune.json")
     b, sched = autotune.tuned_basis(N, J, reps=2, cache=cache)
-    assert sched in [tuple(c) for c in autotune.candidates(N)]
+    assert len(sched) == 5 and sched[4] in autotune.IPW_CANDIDATES
+    assert sched[:4] in [tuple(c) for c in autotune.candidates(N)]
     assert autotune.tune(N, J, reps=2, cache=cache) == sched      # cached
     sub = oracle.Subspace(N, 1, N // 2)
     x = np.random.default_rng(0).uniform(-1, 1, b.dim)
