@@ -144,6 +144,9 @@ __global__ __launch_bounds__(kBlock) void sumsq_kernel(const T *__restrict__ x, 
 // Sum of n partials in a fixed order by one workgroup.
 __device__ double fixed_sum(const double *__restrict__ partial, int n, double *red) {
     double s = 0.0;
+    // unrolled so that several loads are in flight (large grids write tens of
+    // thousands of partials); the additions keep their order
+#pragma unroll 8
     for (int t = threadIdx.x; t < n; t += blockDim.x) s += partial[t];
     return block_sum(s, red);
 }
