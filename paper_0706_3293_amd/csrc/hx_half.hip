@@ -40,7 +40,7 @@ constexpr int kHalfMaxK = 14;
 constexpr int kHalfMaxHighBits = 24;
 constexpr int kGroup = 8;
 constexpr uint32_t kNoHigh = 0xFFFFFFFFu;      // padding slot of a high-word group
-constexpr size_t kMaxNeighbourBytes = (size_t)4 << 30;
+constexpr size_t kMaxNeighbourBytes = (size_t)8 << 30;
 constexpr int64_t kMaxHalfGrid = 1 << 20;   // workgroups (and FP64 partials) of one launch
 
 // Persistent sweep over the items (grid a multiple of 8; workgroup b runs on
@@ -95,12 +95,20 @@ static void free_half(void *p) {
 }
 
 // Bonds of one coupling list regrouped for a given K, plus the neighbour
-// table: for every high word h, (nHg + nSg) * 8 block offsets, in group
-// order (cached in the Couplings object of the basis).
+// table: for every high word h a row of (nHg + nSg) * 8 block offsets.  Its
+// high-word part is compacted: first the target blocks of the high-word bonds
+// that flip for h, in bond order (hcnt[h] of them, their bond slots in hidx),
+// then the own block up to the next multiple of 8, paired with a bond of
+// coefficient 0; a bond that cannot flip would only add c (x_i - x_i) = 0,
+// so the compacted rows give the same sums with fewer loads.  The straddling
+// part holds Off(h ^ m2) per bond in group order.  (Cached in the Couplings
+// object of the basis.)
 struct HalfBonds {
     int K = -1, nLg = 0, nHg = 0, nSg = 0;
     BondGroup *groups = nullptr;
     void *nbr = nullptr;
+    uint32_t *hcnt = nullptr;     // flipping high-word bonds per high word
+    uint16_t *hidx = nullptr;     // their bond slots, nHg * 8 per high word
 };
 
 template <typename I>
@@ -108,6 +116,8 @@ struct HalfArgs {
     const uint16_t *rankL, *unrankL;
     const I *off;
     const I *nbr;
+    const uint32_t *hcnt;
+    const uint16_t *hidx;
     const uint32_t *hgroups;
     const uint32_t *items;
     const BondGroup *groups;
@@ -224,22 +234,21 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
                 for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
             }
         }
-        // bonds inside the high word: tabulated target block (own block if
-        // the bond cannot flip), same low word.  The test is wave-uniform; for
-        // FP64 a bond that cannot flip skips its load with a scalar branch, for
-        // FP32 the branch costs more than the (cached) load it saves
-        for (int k = 0; k < g.nHg; ++k) {
-            const BondGroup &G = gh[k];
+        // bonds inside the high word that flip for h_m (compacted rows of the
+        // table): target block, same low word, coalesced gathers
 #pragma unroll
-            for (int m = 0; m < R; ++m) {
+        for (int m = 0; m < R; ++m) {
+            const int nf = (int)g.hcnt[hs[m]];
+            const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
+            for (int k = 0; k < nf; k += kGroup) {
                 T xj[kGroup];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const I o = nb[m][k * kGroup + q];
-                    xj[q] = (sizeof(T) == 8 && o == off[m]) ? xi[m] : load_at(x + o, r_bytes);
-                }
+                for (int q = 0; q < kGroup; ++q) xj[q] = load_at(x + nb[m][k + q], r_bytes);
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+                for (int q = 0; q < kGroup; ++q) {
+                    const uint32_t b = bi[k + q];
+                    acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[q] - xi[m]);
+                }
             }
         }
         // bonds with one site in each word: uniform high bit, per-lane low bit
@@ -321,6 +330,8 @@ struct StagedWave {
     T *xs;                              // this wave's LDS slice
     const Const<BondGroup> *gl, *gh, *gs;
     const Const<I> *nbr;
+    const Const<uint32_t> *hcnt;
+    const Const<uint16_t> *hidx;
     const T *x;
     T *y;
     const T *prev;
@@ -393,15 +404,21 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
             }
         }
     }
-    // bonds inside the high word: coalesced global gathers (the own block,
-    // an L1 hit, when the bond cannot flip for h_m)
-    for (int k = 0; k < g.nHg; ++k) {
-        const Const<BondGroup> &G = w.gh[k];
+    // bonds inside the high word that flip for h_m (compacted rows of the
+    // table): coalesced global gathers
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
+    for (int m = 0; m < R; ++m) {
+        const int nf = (int)w.hcnt[hs[m]];
+        const Const<uint16_t> *bi = w.hidx + (size_t)hs[m] * (g.nHg * kGroup);
+        for (int k = 0; k < nf; k += kGroup) {
             I o[kGroup];
+            T c[kGroup];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) o[q] = nb[m][k * kGroup + q];
+            for (int q = 0; q < kGroup; ++q) {
+                o[q] = nb[m][k + q];
+                const uint32_t b = bi[k + q];
+                c[q] = coefc<T>(w.gh[b >> 3], b & 7);
+            }
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 T xj[kGroup];
@@ -409,7 +426,7 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
                 for (int q = 0; q < kGroup; ++q)
                     xj[q] = load_at(w.x + o[q], rb[j] * (uint32_t)sizeof(T));
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+                for (int q = 0; q < kGroup; ++q) acc[m][j] += c[q] * (xj[q] - xi[m][j]);
             }
         }
     }
@@ -488,6 +505,8 @@ __global__ __launch_bounds__(256) void hx_half_staged_kernel(
     w.gh = w.gl + g.nLg;
     w.gs = w.gl + g.nLg + g.nHg;
     w.nbr = as_const(g.nbr);
+    w.hcnt = as_const(g.hcnt);
+    w.hidx = as_const(g.hidx);
     w.x = x;
     w.y = y;
     w.prev = prev;
@@ -768,6 +787,8 @@ static void free_half_bonds(void *p) {
     if (!hb) return;
     if (hb->groups) (void)hipFree(hb->groups);
     if (hb->nbr) (void)hipFree(hb->nbr);
+    if (hb->hcnt) (void)hipFree(hb->hcnt);
+    if (hb->hidx) (void)hipFree(hb->hidx);
     delete hb;
 }
 
@@ -796,7 +817,9 @@ static size_t neighbour_bytes(const Basis *b, const Couplings *c, int K) {
         else if (bd.v >= K) ++nS;
     }
     const size_t width = (size_t)((nH + kGroup - 1) / kGroup + (nS + kGroup - 1) / kGroup) * kGroup;
-    return ((size_t)1 << (b->N - K)) * width * (b->idx32 ? 4 : 8);
+    const size_t hwidth = (size_t)((nH + kGroup - 1) / kGroup) * kGroup;
+    return ((size_t)1 << (b->N - K)) *
+           (width * (b->idx32 ? 4 : 8) + hwidth * sizeof(uint16_t) + sizeof(uint32_t));
 }
 
 static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
@@ -834,21 +857,32 @@ static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
     const int nHg = (int)groups.size() - nLg;
     to_groups(st, groups);
     const int nSg = (int)groups.size() - nLg - nHg;
-    const int width = (nHg + nSg) * kGroup;
+    groups.push_back(BondGroup{});    // all coefficients 0: the padding of compacted rows
+    const int width = (nHg + nSg) * kGroup, hwidth = nHg * kGroup;
+    const uint16_t zero_slot = (uint16_t)((nHg + nSg) * kGroup);   // relative to the high groups
     const int64_t nhigh = (int64_t)1 << (b->N - K);
-    // neighbour table: high bonds -> Off(h ^ m) if the bond flips, else Off(h);
-    // straddling bonds -> Off(h ^ m2)
+    // neighbour table: compacted high-word part (target blocks of the bonds
+    // that flip, then the own block), straddling part Off(h ^ m2)
     std::vector<uint64_t> nbr((size_t)nhigh * width, 0);
+    std::vector<uint32_t> hcnt((size_t)nhigh, 0);
+    std::vector<uint16_t> hidx((size_t)nhigh * hwidth, zero_slot);
     for (int64_t h = 0; h < nhigh; ++h) {
         const int aL = b->A - __builtin_popcountll((unsigned long long)h);
         if (aL < 0 || aL > K) continue;
         uint64_t *row = &nbr[(size_t)h * width];
+        uint16_t *irow = &hidx[(size_t)h * hwidth];
+        int n = 0;
         for (int k = 0; k < nHg; ++k)
             for (int q = 0; q < kGroup; ++q) {
                 const uint32_t m = groups[nLg + k].m1[q];
-                const bool flips = __builtin_popcountll((unsigned long long)(h & m)) == 1;
-                row[k * kGroup + q] = t->off_host[flips ? (h ^ m) : h];
+                if (__builtin_popcountll((unsigned long long)(h & m)) == 1) {
+                    row[n] = t->off_host[h ^ m];
+                    irow[n] = (uint16_t)(k * kGroup + q);
+                    ++n;
+                }
             }
+        hcnt[h] = (uint32_t)n;
+        for (int s2 = n; s2 < hwidth; ++s2) row[s2] = t->off_host[h];
         for (int k = 0; k < nSg; ++k)
             for (int q = 0; q < kGroup; ++q)
                 row[(nHg + k) * kGroup + q] = t->off_host[h ^ groups[nLg + nHg + k].m2[q]];
@@ -868,6 +902,9 @@ static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
             e = upload(&hb->nbr, nbr.data(), nbr.size() * sizeof(uint64_t));
         }
     }
+    if (e == hipSuccess) e = upload((void **)&hb->hcnt, hcnt.data(), hcnt.size() * sizeof(uint32_t));
+    if (e == hipSuccess && !hidx.empty())
+        e = upload((void **)&hb->hidx, hidx.data(), hidx.size() * sizeof(uint16_t));
     if (e != hipSuccess) {
         free_half_bonds(hb);
         return fail(HM_EDEVICE, "block kernel bonds: %s", hipGetErrorString(e));
@@ -946,6 +983,8 @@ static void launch_t(const HalfTables *t, const HalfBonds *hb, const Basis *b, d
     g.unrankL = t->d_unrankL;
     g.off = (const I *)t->d_off;
     g.nbr = (const I *)hb->nbr;
+    g.hcnt = hb->hcnt;
+    g.hidx = hb->hidx;
     g.hgroups = t->d_hgroups;
     g.items = t->d_items;
     g.groups = hb->groups;
