@@ -235,19 +235,48 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             }
         }
         // bonds inside the high word that flip for h_m (compacted rows of the
-        // table): target block, same low word, coalesced gathers
+        // table): target block, same low word, coalesced gathers.  Up to 4
+        // rows per lane go through their rows of the table together, up to
+        // the longest (shorter rows continue with their own block and
+        // coefficient 0), so that R groups of loads are in flight at once;
+        // with 8 rows per lane that costs too many registers, and the rows
+        // go one after another.  The sums are the same either way.
+        if constexpr (R <= 4) {
+            const uint16_t *__restrict__ bi[R];
+            int nmax = 0;
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int nf = (int)g.hcnt[hs[m]];
-            const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-            for (int k = 0; k < nf; k += kGroup) {
-                T xj[kGroup];
+            for (int m = 0; m < R; ++m) {
+                nmax = max(nmax, (int)g.hcnt[hs[m]]);
+                bi[m] = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
+            }
+            for (int k = 0; k < nmax; k += kGroup) {
+                T xj[R][kGroup];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) xj[q] = load_at(x + nb[m][k + q], r_bytes);
+                for (int m = 0; m < R; ++m)
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const uint32_t b = bi[k + q];
-                    acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[q] - xi[m]);
+                    for (int q = 0; q < kGroup; ++q) xj[m][q] = load_at(x + nb[m][k + q], r_bytes);
+#pragma unroll
+                for (int m = 0; m < R; ++m)
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) {
+                        const uint32_t b = bi[m][k + q];
+                        acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[m][q] - xi[m]);
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int nf = (int)g.hcnt[hs[m]];
+                const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
+                for (int k = 0; k < nf; k += kGroup) {
+                    T xj[kGroup];
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) xj[q] = load_at(x + nb[m][k + q], r_bytes);
+#pragma unroll
+                    for (int q = 0; q < kGroup; ++q) {
+                        const uint32_t b = bi[k + q];
+                        acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[q] - xi[m]);
+                    }
                 }
             }
         }
