@@ -75,7 +75,7 @@ constexpr int64_t kSmallMaxDim = 1 << 20;
 struct Layout {
     size_t lz, alpha, beta, sigma, cprev, coef, hcoef, partial, bpart, r0, r1, r2, V, states,
         total;
-    int grid_vec, nparts;
+    int grid_vec, grid_b, nparts;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -88,14 +88,28 @@ static int vec_grid(int64_t n) {
     return (int)g;
 }
 
+// Workgroups of pass B: about 8 16-byte vectors per thread, so that long
+// vectors run on many more workgroups than fit at once and the dispatcher
+// keeps every CU busy to the end (601 M FP32 rows: 1.51 ms on 2048
+// workgroups, 1.36 ms on 65536).
+constexpr int64_t kMaxGridB = 65536;
+static int pass_b_grid(int64_t n, size_t es) {
+    const int64_t per = (int64_t)(16 / es) * kBlock * 8;
+    int64_t g = std::min<int64_t>((n + per - 1) / per, kMaxGridB);
+    g = std::max<int64_t>(g, vec_grid(n));
+    if (g >= kXcds) g -= g % kXcds;
+    return (int)g;
+}
+
 // Workspace layout; the partial-sum area holds one entry per workgroup of
-// whichever H x kernel may run (kMaxGrid, or the block kernel's grid when its
+// pass B and of whichever H x kernel may run (kMaxGrid, or the block kernel's grid when its
 // schedule asks for more), so the layout does not depend on the kernel choice.
 static Layout layout(const Basis *b, int steps, int prec, int reorth) {
     Layout L{};
     const size_t es = prec == HM_PREC_F64 ? 8 : 4;
     L.grid_vec = vec_grid(b->dim);
-    L.nparts = std::max(kMaxGrid, half_supported(b) ? hx_half_grid(b) : 0);
+    L.grid_b = pass_b_grid(b->dim, es);
+    L.nparts = std::max({kMaxGrid, L.grid_b, half_supported(b) ? hx_half_grid(b) : 0});
     size_t partial_len = (size_t)L.nparts;
     if (reorth) partial_len = std::max(partial_len, (size_t)L.grid_vec * (size_t)steps);
     size_t off = 0;
@@ -141,15 +155,31 @@ __global__ __launch_bounds__(kBlock) void sumsq_kernel(const T *__restrict__ x, 
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Sum of n partials in a fixed order by one workgroup.
+// Sum of n partials in a fixed order by one workgroup: thread t adds
+// partials t, t + blockDim, t + 2 blockDim, ... in that order, then the wave
+// and workgroup sums combine the threads in a fixed order.
 __device__ double fixed_sum(const double *__restrict__ partial, int n, double *red) {
+    // 16 loads in flight per thread before their additions (large grids of
+    // the H x pass write up to 2^20 partials; their loads are served from
+    // beyond L2, since other XCDs wrote them)
+    constexpr int U = 16;
+    const int stride = blockDim.x;
     double s = 0.0;
-    // unrolled so that several loads are in flight (large grids write tens of
-    // thousands of partials); the additions keep their order
-#pragma unroll 8
-    for (int t = threadIdx.x; t < n; t += blockDim.x) s += partial[t];
+    int t = threadIdx.x;
+    for (; t + (U - 1) * stride < n; t += U * stride) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = partial[t + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
+    for (; t < n; t += stride) s += partial[t];
     return block_sum(s, red);
 }
+
+// Threads of the finish that sums the H x pass's partials (one per workgroup
+// of that pass, up to 2^20): 16 waves, the most block_sum combines.
+constexpr int kFinishBlock = 1024;
 
 __global__ __launch_bounds__(kBlock) void finish_init(LzDev *lz, const double *partial, int n,
                                                       double *sigma, double *cprev,
@@ -181,8 +211,8 @@ __global__ __launch_bounds__(kBlock) void init_write(const double *__restrict__ 
         r[i] = (T)(v0[i] * inv);
 }
 
-__global__ __launch_bounds__(kBlock) void finish_alpha(LzDev *lz, const double *partial,
-                                                       int n, double *alpha, int k) {
+__global__ __launch_bounds__(kFinishBlock) void finish_alpha(LzDev *lz, const double *partial,
+                                                             int n, double *alpha, int k) {
     if (lz->stopped) return;
     __shared__ double red[16];
     const double s = fixed_sum(partial, n, red);
@@ -242,9 +272,10 @@ __global__ __launch_bounds__(kBlock) void pass_b(T *__restrict__ w, const T *__r
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void finish_beta(LzDev *lz, const double *partial, int n,
-                                                      const double *alpha, double *beta,
-                                                      double *sigma, double *cprev, int k) {
+__global__ __launch_bounds__(kFinishBlock) void finish_beta(LzDev *lz, const double *partial,
+                                                            int n, const double *alpha,
+                                                            double *beta, double *sigma,
+                                                            double *cprev, int k) {
     if (lz->stopped) return;
     __shared__ double red[16];
     const double s = fixed_sum(partial, n, red);
@@ -613,7 +644,7 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
     double *partial = (double *)(R.w + R.L.partial), *bpart = (double *)(R.w + R.L.bpart);
     T *buf[3] = {(T *)(R.w + R.L.r0), (T *)(R.w + R.L.r1), (T *)(R.w + R.L.r2)};
     T *V = (T *)(R.w + R.L.V);
-    const int G = R.L.grid_vec;
+    const int G = R.L.grid_vec, Gb = R.L.grid_b;
     const int Ghx = hx_partial_count(b, R.kernel);
     const int dtype = R.prec == HM_PREC_F64 ? HM_F64 : HM_F32;
     for (int k = k0; k < k1; ++k) {
@@ -644,13 +675,13 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
             hipLaunchKernelGGL((pass_b_fused<T, 0>), dim3(G), dim3(kBlock), 0, R.st, wn, rk, n,
                                lz, partial, Ghx, alpha, beta, sigma, cprev, k, bpart);
         } else {
-            hipLaunchKernelGGL(finish_alpha, dim3(1), dim3(kBlock), 0, R.st, lz, partial, Ghx,
+            hipLaunchKernelGGL(finish_alpha, dim3(1), dim3(kFinishBlock), 0, R.st, lz, partial, Ghx,
                                alpha, k);
-            hipLaunchKernelGGL(pass_b<T>, dim3(G), dim3(kBlock), 0, R.st, wn, rk, n, lz, alpha,
+            hipLaunchKernelGGL(pass_b<T>, dim3(Gb), dim3(kBlock), 0, R.st, wn, rk, n, lz, alpha,
                                sigma, k, partial);
         }
         if (!R.reorth) {
-            hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G,
+            hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kFinishBlock), 0, R.st, lz, partial, Gb,
                                alpha, beta, sigma, cprev, k);
             continue;
         }
@@ -665,7 +696,7 @@ static int enqueue_steps(Run &R, int k0, int k1, std::vector<hipEvent_t> *ev) {
         }
         hipLaunchKernelGGL(sumsq_kernel<T>, dim3(G), dim3(kBlock), 0, R.st, wn, n, partial,
                            &lz->stopped);
-        hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kBlock), 0, R.st, lz, partial, G, alpha,
+        hipLaunchKernelGGL(finish_beta, dim3(1), dim3(kFinishBlock), 0, R.st, lz, partial, G, alpha,
                            beta, sigma, cprev, k);
     }
     HM_HIP(hipGetLastError());
