@@ -29,6 +29,7 @@
 // Each row is written by one lane; workgroups are persistent, and the eight
 // XCDs take turns on runs of consecutive items so that they sweep x together.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "device_common.h"
@@ -105,6 +106,7 @@ static void free_half(void *p) {
 // object of the basis.)
 struct HalfBonds {
     int K = -1, nLg = 0, nHg = 0, nSg = 0;
+    int nL = 0, nS = 0;           // low-word and straddling bonds (slots in use)
     BondGroup *groups = nullptr;
     void *nbr = nullptr;
     uint32_t *hcnt = nullptr;     // flipping high-word bonds per high word
@@ -123,6 +125,7 @@ struct HalfArgs {
     const BondGroup *groups;
     uint32_t n_items;
     int K, A, nLg, nHg, nSg, width;
+    int nL, nS;
     double shift;
     int class_start[kHalfMaxK + 2];
     int class_size[kHalfMaxK + 2];
@@ -132,6 +135,23 @@ struct HalfArgs {
 template <typename T>
 __device__ __forceinline__ T load_at(const T *__restrict__ base, uint32_t byte_off) {
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+// Visits slots [0, n) of a run of 8-slot groups (n wave-uniform) in pieces:
+// whole groups, then at most one piece of 4 and pieces of 2, each inside one
+// group; f(std::integral_constant<int, W>, first slot).  The slots after n up
+// to the next even number are padding (a bond that never flips, or the own
+// block with coefficient 0), so every piece gives the sums of the slots in
+// use, in slot order, with at most one padding slot instead of up to seven.
+template <typename F>
+__device__ __forceinline__ void for_pieces(int n, F &&f) {
+    int k = 0;
+    for (; k + kGroup <= n; k += kGroup) f(std::integral_constant<int, kGroup>{}, k);
+    if (n - k >= 4) {
+        f(std::integral_constant<int, 4>{}, k);
+        k += 4;
+    }
+    for (; k < n; k += 2) f(std::integral_constant<int, 2>{}, k);
 }
 
 template <typename T> __device__ __forceinline__ T coef(const BondGroup &g, int q);
@@ -214,26 +234,28 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             acc[m] = 0;
         }
         // bonds inside the low word: the test and rankL(L ^ m) once per lane
-        for (int k = 0; k < g.nLg; ++k) {
-            const BondGroup &G = gl[k];
-            uint32_t mk[kGroup], idx[kGroup];
+        for_pieces(g.nL, [&](auto Wc, int k) {
+            constexpr int W = decltype(Wc)::value;
+            const BondGroup &G = gl[k / kGroup];
+            const int q0 = W == kGroup ? 0 : k % kGroup;
+            uint32_t mk[W], idx[W];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) mk[q] = G.m1[q];
+            for (int q = 0; q < W; ++q) mk[q] = G.m1[q0 + q];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) idx[q] = rankL[L ^ mk[q]];
+            for (int q = 0; q < W; ++q) idx[q] = rankL[L ^ mk[q]];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q)
+            for (int q = 0; q < W; ++q)
                 idx[q] = __popc(L & mk[q]) == 1 ? idx[q] * (uint32_t)sizeof(T) : r_bytes;
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const T *__restrict__ xb = x + off[m];
-                T xj[kGroup];
+                T xj[W];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) xj[q] = load_at(xb, idx[q]);
+                for (int q = 0; q < W; ++q) xj[q] = load_at(xb, idx[q]);
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+                for (int q = 0; q < W; ++q) acc[m] += coef<T>(G, q0 + q) * (xj[q] - xi[m]);
             }
-        }
+        });
         // bonds inside the high word that flip for h_m (compacted rows of the
         // table): target block, same low word, coalesced gathers.  Up to 4
         // rows per lane go through their rows of the table together, up to
@@ -249,64 +271,69 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
                 nmax = max(nmax, (int)g.hcnt[hs[m]]);
                 bi[m] = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
             }
-            for (int k = 0; k < nmax; k += kGroup) {
-                T xj[R][kGroup];
+            for_pieces(nmax, [&](auto Wc, int k) {
+                constexpr int W = decltype(Wc)::value;
+                T xj[R][W];
 #pragma unroll
                 for (int m = 0; m < R; ++m)
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) xj[m][q] = load_at(x + nb[m][k + q], r_bytes);
+                    for (int q = 0; q < W; ++q) xj[m][q] = load_at(x + nb[m][k + q], r_bytes);
 #pragma unroll
                 for (int m = 0; m < R; ++m)
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) {
+                    for (int q = 0; q < W; ++q) {
                         const uint32_t b = bi[m][k + q];
                         acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[m][q] - xi[m]);
                     }
-            }
+            });
         } else {
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const int nf = (int)g.hcnt[hs[m]];
                 const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-                for (int k = 0; k < nf; k += kGroup) {
-                    T xj[kGroup];
+                for_pieces(nf, [&](auto Wc, int k) {
+                    constexpr int W = decltype(Wc)::value;
+                    T xj[W];
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) xj[q] = load_at(x + nb[m][k + q], r_bytes);
+                    for (int q = 0; q < W; ++q) xj[q] = load_at(x + nb[m][k + q], r_bytes);
 #pragma unroll
-                    for (int q = 0; q < kGroup; ++q) {
+                    for (int q = 0; q < W; ++q) {
                         const uint32_t b = bi[k + q];
                         acc[m] += coef<T>(gh[b >> 3], b & 7) * (xj[q] - xi[m]);
                     }
-                }
+                });
             }
         }
         // bonds with one site in each word: uniform high bit, per-lane low bit
-        for (int k = 0; k < g.nSg; ++k) {
-            const BondGroup &G = gs[k];
-            uint32_t ml[kGroup], lb[kGroup], rk[kGroup];
+        for_pieces(g.nS, [&](auto Wc, int k) {
+            constexpr int W = decltype(Wc)::value;
+            const BondGroup &G = gs[k / kGroup];
+            const int q0 = W == kGroup ? 0 : k % kGroup;
+            uint32_t ml[W], lb[W], rk[W];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) ml[q] = G.m1[q];
+            for (int q = 0; q < W; ++q) ml[q] = G.m1[q0 + q];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
+            for (int q = 0; q < W; ++q) {
                 rk[q] = rankL[L ^ ml[q]];
                 lb[q] = L & ml[q];
             }
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const I *__restrict__ nbs = nb[m] + (g.nHg + k) * kGroup;
+                const I *__restrict__ nbs = nb[m] + g.nHg * kGroup + k;
                 const I own = off[m] + (I)r;
-                T xj[kGroup];
+                T xj[W];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
+                for (int q = 0; q < W; ++q) {
                     // the low-bit value that differs from the high bit;
                     // padding entries (ml = 0) get an impossible value
-                    const uint32_t want = ml[q] == 0 ? 1u : ((hs[m] & G.m2[q]) ? 0u : ml[q]);
+                    const uint32_t want =
+                        ml[q] == 0 ? 1u : ((hs[m] & G.m2[q0 + q]) ? 0u : ml[q]);
                     xj[q] = x[lb[q] == want ? nbs[q] + (I)rk[q] : own];
                 }
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m] += coef<T>(G, q) * (xj[q] - xi[m]);
+                for (int q = 0; q < W; ++q) acc[m] += coef<T>(G, q0 + q) * (xj[q] - xi[m]);
             }
-        }
+        });
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             if (live && valid[m]) {
@@ -353,6 +380,14 @@ template <> __device__ __forceinline__ double coefc<double>(const Const<BondGrou
 // arithmetic per row as hx_half_kernel: acc accumulates the
 // bonds in the same order, so both kernels give bitwise equal results.
 // Shared state of one wave of the staged kernel.
+
+// Visits slots [0, n) of a run of 8-slot groups in whole groups (padding
+// slots of the last group included); f as for for_pieces.
+template <typename F>
+__device__ __forceinline__ void for_groups(int n, F &&f) {
+    for (int k = 0; k < n; k += kGroup) f(std::integral_constant<int, kGroup>{}, k);
+}
+
 template <typename T, typename I>
 struct StagedWave {
     const uint16_t *rankL, *unrankL;
@@ -410,84 +445,98 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
             if (live[j]) w.xs[m * kSlice + rb[j]] = xi[m][j];
     __builtin_amdgcn_wave_barrier();
     // bonds inside the low word: LDS gathers
-    for (int k = 0; k < g.nLg; ++k) {
-        const Const<BondGroup> &G = w.gl[k];
-        uint32_t mk[kGroup];
+    for_pieces(g.nL, [&](auto Wc, int k) {
+        constexpr int W = decltype(Wc)::value;
+        const Const<BondGroup> &G = w.gl[k / kGroup];
+        const int q0 = W == kGroup ? 0 : k % kGroup;
+        uint32_t mk[W];
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q) mk[q] = G.m1[q];
+        for (int q = 0; q < W; ++q) mk[q] = G.m1[q0 + q];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            uint32_t idx[kGroup];
+            uint32_t idx[W];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
+            for (int q = 0; q < W; ++q) {
                 const uint32_t t2 = w.rankL[L[j] ^ mk[q]];
                 idx[q] = __popc(L[j] & mk[q]) == 1 ? t2 : rb[j];
             }
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                T xj[kGroup];
+                T xj[W];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) xj[q] = w.xs[m * kSlice + idx[q]];
+                for (int q = 0; q < W; ++q) xj[q] = w.xs[m * kSlice + idx[q]];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+                for (int q = 0; q < W; ++q)
+                    acc[m][j] += coefc<T>(G, q0 + q) * (xj[q] - xi[m][j]);
             }
         }
-    }
+    });
     // bonds inside the high word that flip for h_m (compacted rows of the
     // table): coalesced global gathers
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int nf = (int)w.hcnt[hs[m]];
         const Const<uint16_t> *bi = w.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-        for (int k = 0; k < nf; k += kGroup) {
-            I o[kGroup];
-            T c[kGroup];
+        for_pieces(nf, [&](auto Wc, int k) {
+            constexpr int W = decltype(Wc)::value;
+            I o[W];
+            T c[W];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
+            for (int q = 0; q < W; ++q) {
                 o[q] = nb[m][k + q];
                 const uint32_t b = bi[k + q];
                 c[q] = coefc<T>(w.gh[b >> 3], b & 7);
             }
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                T xj[kGroup];
+                T xj[W];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q)
+                for (int q = 0; q < W; ++q)
                     xj[q] = load_at(w.x + o[q], rb[j] * (uint32_t)sizeof(T));
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m][j] += c[q] * (xj[q] - xi[m][j]);
+                for (int q = 0; q < W; ++q) acc[m][j] += c[q] * (xj[q] - xi[m][j]);
             }
-        }
+        });
     }
     // bonds with one site in each word: uniform high bit, per-lane low bit
-    for (int k = 0; k < g.nSg; ++k) {
-        const Const<BondGroup> &G = w.gs[k];
-        uint32_t ml[kGroup];
+    auto straddle = [&](auto Wc, int k) {
+        constexpr int W = decltype(Wc)::value;
+        const Const<BondGroup> &G = w.gs[k / kGroup];
+        const int q0 = W == kGroup ? 0 : k % kGroup;
+        uint32_t ml[W];
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q) ml[q] = G.m1[q];
+        for (int q = 0; q < W; ++q) ml[q] = G.m1[q0 + q];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            uint32_t rk[kGroup], lb[kGroup];
+            uint32_t rk[W], lb[W];
 #pragma unroll
-            for (int q = 0; q < kGroup; ++q) {
+            for (int q = 0; q < W; ++q) {
                 rk[q] = w.rankL[L[j] ^ ml[q]];
                 lb[q] = L[j] & ml[q];
             }
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const Const<I> *nbs = nb[m] + (g.nHg + k) * kGroup;
+                const Const<I> *nbs = nb[m] + g.nHg * kGroup + k;
                 const I own = off[m] + (I)rb[j];
-                T xj[kGroup];
+                T xj[W];
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) {
-                    const uint32_t want = ml[q] == 0 ? 1u : ((hs[m] & G.m2[q]) ? 0u : ml[q]);
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t want =
+                        ml[q] == 0 ? 1u : ((hs[m] & G.m2[q0 + q]) ? 0u : ml[q]);
                     xj[q] = w.x[lb[q] == want ? nbs[q] + (I)rk[q] : own];
                 }
 #pragma unroll
-                for (int q = 0; q < kGroup; ++q) acc[m][j] += coefc<T>(G, q) * (xj[q] - xi[m][j]);
+                for (int q = 0; q < W; ++q)
+                    acc[m][j] += coefc<T>(G, q0 + q) * (xj[q] - xi[m][j]);
             }
         }
-    }
+    };
+    // FP64 takes the pieces; in FP32 the extra code of the pieces here would
+    // need 4 more VGPRs, and with the FP64 dot of a Lanczos step that is one
+    // VGPR more than 4 waves per SIMD allow (N=32 pass A: 10.64 ms by whole
+    // groups, 12.8-13.0 ms with pieces at 3 waves)
+    if constexpr (sizeof(T) == 8) for_pieces(g.nS, straddle);
+    else for_groups(g.nS, straddle);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
 #pragma unroll
@@ -921,6 +970,8 @@ static int half_bonds(Basis *b, const Couplings *c, const HalfTables *t,
     hb->nLg = nLg;
     hb->nHg = nHg;
     hb->nSg = nSg;
+    hb->nL = (int)lo.size();
+    hb->nS = (int)st.size();
     hipError_t e = hipSuccess;
     if (!groups.empty()) e = upload((void **)&hb->groups, groups.data(), groups.size() * sizeof(BondGroup));
     if (e == hipSuccess && !nbr.empty()) {
@@ -1023,6 +1074,8 @@ static void launch_t(const HalfTables *t, const HalfBonds *hb, const Basis *b, d
     g.nLg = hb->nLg;
     g.nHg = hb->nHg;
     g.nSg = hb->nSg;
+    g.nL = hb->nL;
+    g.nS = hb->nS;
     g.width = (hb->nHg + hb->nSg) * kGroup;
     g.shift = shift;
     for (int a = 0; a <= kHalfMaxK + 1; ++a) {
