@@ -137,17 +137,20 @@ __device__ __forceinline__ T load_at(const T *__restrict__ base, uint32_t byte_o
     return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
 }
 
-// Visits slots [0, n) of a run of 8-slot groups (n wave-uniform) in pieces:
-// whole groups, then at most one piece of 4 and pieces of 2, each inside one
-// group; f(std::integral_constant<int, W>, first slot).  The slots after n up
-// to the next even number are padding (a bond that never flips, or the own
-// block with coefficient 0), so every piece gives the sums of the slots in
-// use, in slot order, with at most one padding slot instead of up to seven.
-template <typename F>
+// Visits slots [0, n) of a run of 8-slot groups (n wave-uniform) in pieces
+// of at most MaxW (8 or 4) slots: pieces of MaxW, then at most one piece of
+// 4 and pieces of 2, each inside one group; f(std::integral_constant<int, W>,
+// first slot).  The slots after n up to the next even number are padding (a
+// bond that never flips, or the own block with coefficient 0), so every
+// piece gives the sums of the slots in use, in slot order, with at most one
+// padding slot instead of up to seven.  Narrower pieces keep fewer loads in
+// flight per wave but need fewer registers, so more waves fit.
+template <int MaxW, typename F>
 __device__ __forceinline__ void for_pieces(int n, F &&f) {
+    static_assert(MaxW == kGroup || MaxW == 4, "pieces of 8 or 4 slots");
     int k = 0;
-    for (; k + kGroup <= n; k += kGroup) f(std::integral_constant<int, kGroup>{}, k);
-    if (n - k >= 4) {
+    for (; k + MaxW <= n; k += MaxW) f(std::integral_constant<int, MaxW>{}, k);
+    if (MaxW == kGroup && n - k >= 4) {
         f(std::integral_constant<int, 4>{}, k);
         k += 4;
     }
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             acc[m] = 0;
         }
         // bonds inside the low word: the test and rankL(L ^ m) once per lane
-        for_pieces(g.nL, [&](auto Wc, int k) {
+        for_pieces<kGroup>(g.nL, [&](auto Wc, int k) {
             constexpr int W = decltype(Wc)::value;
             const BondGroup &G = gl[k / kGroup];
             const int q0 = W == kGroup ? 0 : k % kGroup;
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
                 nmax = max(nmax, (int)g.hcnt[hs[m]]);
                 bi[m] = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
             }
-            for_pieces(nmax, [&](auto Wc, int k) {
+            for_pieces<kGroup>(nmax, [&](auto Wc, int k) {
                 constexpr int W = decltype(Wc)::value;
                 T xj[R][W];
 #pragma unroll
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             for (int m = 0; m < R; ++m) {
                 const int nf = (int)g.hcnt[hs[m]];
                 const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-                for_pieces(nf, [&](auto Wc, int k) {
+                for_pieces<kGroup>(nf, [&](auto Wc, int k) {
                     constexpr int W = decltype(Wc)::value;
                     T xj[W];
 #pragma unroll
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             }
         }
         // bonds with one site in each word: uniform high bit, per-lane low bit
-        for_pieces(g.nS, [&](auto Wc, int k) {
+        for_pieces<kGroup>(g.nS, [&](auto Wc, int k) {
             constexpr int W = decltype(Wc)::value;
             const BondGroup &G = gs[k / kGroup];
             const int q0 = W == kGroup ? 0 : k % kGroup;
@@ -380,14 +383,6 @@ template <> __device__ __forceinline__ double coefc<double>(const Const<BondGrou
 // arithmetic per row as hx_half_kernel: acc accumulates the
 // bonds in the same order, so both kernels give bitwise equal results.
 // Shared state of one wave of the staged kernel.
-
-// Visits slots [0, n) of a run of 8-slot groups in whole groups (padding
-// slots of the last group included); f as for for_pieces.
-template <typename F>
-__device__ __forceinline__ void for_groups(int n, F &&f) {
-    for (int k = 0; k < n; k += kGroup) f(std::integral_constant<int, kGroup>{}, k);
-}
-
 template <typename T, typename I>
 struct StagedWave {
     const uint16_t *rankL, *unrankL;
@@ -444,8 +439,14 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
         for (int j = 0; j < J; ++j)
             if (live[j]) w.xs[m * kSlice + rb[j]] = xi[m][j];
     __builtin_amdgcn_wave_barrier();
+    // Widest piece of each slot list.  Pieces of 8 keep more loads in flight
+    // per wave, pieces of 4 need fewer registers, so more waves fit; measured
+    // on the N=32 pass A of a Lanczos step (FP32 89 VGPRs, 5 waves per SIMD,
+    // 9.75 ms against 10.39 ms with pieces of 8 at 117 VGPRs; FP64 96 VGPRs,
+    // 17.09 against 17.83 ms).
+    constexpr int kLowW = sizeof(T) == 4 ? 4 : kGroup, kHighW = 4, kStrW = 4;
     // bonds inside the low word: LDS gathers
-    for_pieces(g.nL, [&](auto Wc, int k) {
+    for_pieces<kLowW>(g.nL, [&](auto Wc, int k) {
         constexpr int W = decltype(Wc)::value;
         const Const<BondGroup> &G = w.gl[k / kGroup];
         const int q0 = W == kGroup ? 0 : k % kGroup;
@@ -477,7 +478,7 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
     for (int m = 0; m < R; ++m) {
         const int nf = (int)w.hcnt[hs[m]];
         const Const<uint16_t> *bi = w.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-        for_pieces(nf, [&](auto Wc, int k) {
+        for_pieces<kHighW>(nf, [&](auto Wc, int k) {
             constexpr int W = decltype(Wc)::value;
             I o[W];
             T c[W];
@@ -531,12 +532,7 @@ __device__ __forceinline__ void staged_item(const HalfArgs<I> &g, const StagedWa
             }
         }
     };
-    // FP64 takes the pieces; in FP32 the extra code of the pieces here would
-    // need 4 more VGPRs, and with the FP64 dot of a Lanczos step that is one
-    // VGPR more than 4 waves per SIMD allow (N=32 pass A: 10.64 ms by whole
-    // groups, 12.8-13.0 ms with pieces at 3 waves)
-    if constexpr (sizeof(T) == 8) for_pieces(g.nS, straddle);
-    else for_groups(g.nS, straddle);
+    for_pieces<kStrW>(g.nS, straddle);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
 #pragma unroll
