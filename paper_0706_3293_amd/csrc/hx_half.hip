@@ -202,6 +202,10 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
     const BondGroup *__restrict__ gl = g.groups;
     const BondGroup *__restrict__ gh = g.groups + g.nLg;
     const BondGroup *__restrict__ gs = g.groups + g.nLg + g.nHg;
+    // widest slot piece: 4 in FP32 (fewer registers, more waves: N=32 R=4
+    // pass 15.2 -> 14.6 ms, N=36 H x 267 -> 260 ms), 8 in FP64 (R=1 28.7 ms
+    // with pieces of 8, 31.9 ms with pieces of 4)
+    constexpr int kW = sizeof(T) == 4 ? 4 : kGroup;
     double dot = 0.0;
     for (uint32_t l = wl;; l += stride) {
         const uint32_t it = by_xcd ? sweep_item(l, x8) : l;
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             acc[m] = 0;
         }
         // bonds inside the low word: the test and rankL(L ^ m) once per lane
-        for_pieces<kGroup>(g.nL, [&](auto Wc, int k) {
+        for_pieces<kW>(g.nL, [&](auto Wc, int k) {
             constexpr int W = decltype(Wc)::value;
             const BondGroup &G = gl[k / kGroup];
             const int q0 = W == kGroup ? 0 : k % kGroup;
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
                 nmax = max(nmax, (int)g.hcnt[hs[m]]);
                 bi[m] = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
             }
-            for_pieces<kGroup>(nmax, [&](auto Wc, int k) {
+            for_pieces<kW>(nmax, [&](auto Wc, int k) {
                 constexpr int W = decltype(Wc)::value;
                 T xj[R][W];
 #pragma unroll
@@ -294,7 +298,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             for (int m = 0; m < R; ++m) {
                 const int nf = (int)g.hcnt[hs[m]];
                 const uint16_t *__restrict__ bi = g.hidx + (size_t)hs[m] * (g.nHg * kGroup);
-                for_pieces<kGroup>(nf, [&](auto Wc, int k) {
+                for_pieces<kW>(nf, [&](auto Wc, int k) {
                     constexpr int W = decltype(Wc)::value;
                     T xj[W];
 #pragma unroll
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(256) void hx_half_kernel(
             }
         }
         // bonds with one site in each word: uniform high bit, per-lane low bit
-        for_pieces<kGroup>(g.nS, [&](auto Wc, int k) {
+        for_pieces<kW>(g.nS, [&](auto Wc, int k) {
             constexpr int W = decltype(Wc)::value;
             const BondGroup &G = gs[k / kGroup];
             const int q0 = W == kGroup ? 0 : k % kGroup;
