@@ -94,7 +94,9 @@ def time_pass_a(b, J, v0, precision, reps):
 def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbose=False):
     """Best (K, block, R, staging, items per wave) for the Lanczos H x pass
     with these couplings; results are cached (entries of older formats are
-    tuned again)."""
+    tuned again).  The trials run Lanczos steps, so they hold an FP64 start
+    vector and the Lanczos workspace (three vectors of dtype) on the device:
+    about 7.2 GB (FP32) and 9.6 GB (FP64) beyond the tables at N=32."""
     key = _key(N, two_M, J, str(dtype))
     table = {}
     if cache and os.path.exists(cache):
