@@ -96,7 +96,8 @@ def tune(N, J, two_M=0, dtype=torch.float32, reps=5, cache=DEFAULT_CACHE, verbos
     with these couplings; results are cached (entries of older formats are
     tuned again).  The trials run Lanczos steps, so they hold an FP64 start
     vector and the Lanczos workspace (three vectors of dtype) on the device:
-    about 7.2 GB (FP32) and 9.6 GB (FP64) beyond the tables at N=32."""
+    20 B per row in FP32 and 32 B per row in FP64 beyond the tables (12 GB
+    and 19 GB at N=32)."""
     key = _key(N, two_M, J, str(dtype))
     table = {}
     if cache and os.path.exists(cache):
